@@ -1,0 +1,188 @@
+"""FP64 CPU oracle for quasi-random frequency sampling (arXiv 2404.02978).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+benchmark's ``cpu_baseline`` leg may import this package.  It shares no code
+with the HIP path (``paper_2404_02978_amd``) and never imports it.
+
+The arithmetic lives in ``qrfs_oracle.c`` (plain double-precision loops,
+compiled with gcc); this module only marshals numpy arrays.  The analytic
+structure functions the estimator converges to live in ``oracle.analytic``.
+
+Parity status of each function (what pins it) is listed in the module
+docstring of ``tests/test_oracle_pins.py``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_d = ctypes.c_double
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_p = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    sig = {
+        "oracle_plastic_number": (None, [_p]),
+        "oracle_r2_increments": (None, [_p]),
+        "oracle_r2_points": (None, [_u64, _u64, _u64, _i64, _p, _p]),
+        "oracle_sample_cartesian": (None, [_u64, _u64, _u64, _i64, _i64, _i32, _d, _p, _p, _p]),
+        "oracle_sample_logpolar": (None, [_u64, _u64, _u64, _i64, _i64, _d, _d, _p, _p, _p]),
+        "oracle_psd_constant": (_d, []),
+        "oracle_psd": (_d, [_i32, _d, _d, _d, _d]),
+        "oracle_aperture_filter": (_d, [_d, _d, _d]),
+        "oracle_weights": (None, [_i32, _d, _d, _d, _i32, _d, _d, _i64, _p, _p, _p, _p]),
+        "oracle_philox4x32_10": (None, [_p, _p, _p]),
+        "oracle_coefficients": (None, [_u64, _u64, _i64, _i32, _p]),
+        "oracle_synthesize": (None, [_i64, _p, _p, _p, _i64, _p, _p, _i64, _i64, _u64, _u64,
+                                     _i32, _p, _p]),
+        "oracle_piston": (None, [_i64, _p, _p, _p, _i64, _p, _p, _p, _p, _i64, _i64, _u64,
+                                 _u64, _i32, _p, _p]),
+        "oracle_diff_piston_sf": (None, [_i64, _p, _p, _p, _i64, _p, _p, _i64, _i64, _u64,
+                                         _u64, _i32, _p, _p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+PSD_KOLMOGOROV = 0
+PSD_VON_KARMAN = 1
+COEF_GAUSS_CS = 0
+COEF_EQ3 = 1
+SEED_HALF = 1 << 63  # s0 = 1/2 in 0.64 fixed point
+
+
+def plastic_number():
+    out = np.zeros(1)
+    _load().oracle_plastic_number(_ptr(out))
+    return float(out[0])
+
+
+def r2_increments():
+    out = np.zeros(2, dtype=np.uint64)
+    _load().oracle_r2_increments(_ptr(out))
+    return int(out[0]), int(out[1])
+
+
+def r2_points(n, index=0, s0x=SEED_HALF, s0y=SEED_HALF):
+    ux = np.zeros(n)
+    uy = np.zeros(n)
+    _load().oracle_r2_points(s0x, s0y, index, n, _ptr(ux), _ptr(uy))
+    return ux, uy
+
+
+def sample_cartesian(n_sets, K, N, df, index=0, s0x=SEED_HALF, s0y=SEED_HALF):
+    n = n_sets * K
+    fx, fy, area = np.zeros(n), np.zeros(n), np.zeros(n)
+    _load().oracle_sample_cartesian(s0x, s0y, index, n_sets, K, N, df, _ptr(fx), _ptr(fy),
+                                    _ptr(area))
+    return fx, fy, area
+
+
+def sample_logpolar(n_sets, K, fmin, fmax, index=0, s0x=SEED_HALF, s0y=SEED_HALF):
+    n = n_sets * K
+    fx, fy, area = np.zeros(n), np.zeros(n), np.zeros(n)
+    _load().oracle_sample_logpolar(s0x, s0y, index, n_sets, K, fmin, fmax, _ptr(fx), _ptr(fy),
+                                   _ptr(area))
+    return fx, fy, area
+
+
+def psd_constant():
+    return _load().oracle_psd_constant()
+
+
+def psd(f, model=PSD_VON_KARMAN, c=None, r0=0.1, L0=25.0):
+    c = psd_constant() if c is None else c
+    lib = _load()
+    f = np.atleast_1d(np.asarray(f, dtype=np.float64))
+    return np.array([lib.oracle_psd(model, c, r0, L0, float(x)) for x in f])
+
+
+def aperture_filter(f, D, d=0.0):
+    lib = _load()
+    f = np.atleast_1d(np.asarray(f, dtype=np.float64))
+    return np.array([lib.oracle_aperture_filter(D, d, float(x)) for x in f])
+
+
+def weights(fx, fy, area, model=PSD_VON_KARMAN, c=None, r0=0.1, L0=25.0, D=None, d=0.0):
+    c = psd_constant() if c is None else c
+    fx, fy, area = _f64(fx), _f64(fy), _f64(area)
+    w = np.zeros(fx.size)
+    has_ap = 0 if D is None else 1
+    _load().oracle_weights(model, c, r0, L0, has_ap, D or 0.0, d, fx.size, _ptr(fx), _ptr(fy),
+                           _ptr(area), _ptr(w))
+    return w
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.zeros(4, dtype=np.uint32)
+    _load().oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def coefficients(seed, realisation, K, mode=COEF_GAUSS_CS):
+    c = np.zeros(2 * K)
+    _load().oracle_coefficients(seed, realisation, K, mode, _ptr(c))
+    return c
+
+
+def synthesize(fx, fy, w, px, py, R, R_block, K=None, seed=0, counter=0,
+               mode=COEF_GAUSS_CS, coef=None):
+    fx, fy, w, px, py = map(_f64, (fx, fy, w, px, py))
+    K = fx.size if K is None else K
+    coef = None if coef is None else _f64(coef)
+    out = np.zeros((R, px.size))
+    _load().oracle_synthesize(K, _ptr(fx), _ptr(fy), _ptr(w), px.size, _ptr(px), _ptr(py), R,
+                              R_block, seed, counter, mode, _ptr(coef), _ptr(out))
+    return out
+
+
+def piston(fx, fy, w, cx, cy, D, d, R, R_block, K=None, seed=0, counter=0,
+           mode=COEF_GAUSS_CS, coef=None):
+    fx, fy, w, cx, cy = map(_f64, (fx, fy, w, cx, cy))
+    D = _f64(np.broadcast_to(D, cx.shape))
+    d = _f64(np.broadcast_to(d, cx.shape))
+    K = fx.size if K is None else K
+    coef = None if coef is None else _f64(coef)
+    out = np.zeros((R, cx.size))
+    _load().oracle_piston(K, _ptr(fx), _ptr(fy), _ptr(w), cx.size, _ptr(cx), _ptr(cy), _ptr(D),
+                          _ptr(d), R, R_block, seed, counter, mode, _ptr(coef), _ptr(out))
+    return out
+
+
+def diff_piston_sf(fx, fy, w, bx, by, R, R_block, K=None, seed=0, counter=0,
+                   mode=COEF_GAUSS_CS):
+    fx, fy, w, bx, by = map(_f64, (fx, fy, w, bx, by))
+    K = fx.size if K is None else K
+    sf = np.zeros(bx.size)
+    se = np.zeros(bx.size)
+    _load().oracle_diff_piston_sf(K, _ptr(fx), _ptr(fy), _ptr(w), bx.size, _ptr(bx), _ptr(by),
+                                  R, R_block, seed, counter, mode, _ptr(sf), _ptr(se))
+    return sf, se

@@ -1,0 +1,370 @@
+/*
+ * qrfs_oracle.c -- plain FP64 CPU oracle for quasi-random frequency sampling
+ * (Berdja, Hadjara, Carbillet, Bernardi, Petrov, "Quasi-Random Frequency
+ * Sampling for Optical Turbulence Simulations", arXiv 2404.02978).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant with the HIP path: every constant below is
+ * derived here from its definition.
+ *
+ * Everything is evaluated in double precision with straightforward loops in
+ * the order the paper states the method; OpenMP only splits independent
+ * realisations across threads (no reordering inside one result).
+ *
+ * Readings of the paper that this file encodes (each is also listed in the
+ * design notes of the repository):
+ *   - R2 sequence (Sec. 3.2, Eq. 6) is kept as an exact 64-bit fixed-point
+ *     Weyl sequence U_n = S0 + n*A mod 2^64, A = round(2^64 * alpha); the
+ *     state is updated before it is used, so point n = index+1 is the first.
+ *   - Cartesian map (Eq. 5): f = delta_f * N * (u - 1/2), i.e. the domain
+ *     width N*delta_f equals 2 max(f) (worked example of Sec. 4.4: 0.25/22
+ *     and 0.25 give N = 44).
+ *   - Coefficients: a_rk, b_rk ~ N(0,1) iid multiply cos and sin of the
+ *     harmonic (the two independent normals of Eq. 2); Eq. 3's literal form
+ *     (one normal amplitude, one uniform phase, factor 2/sqrt 2) is mode 1.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the
+ *     64-bit seed, counter (block, realisation lo, realisation hi, 0);
+ *     uniforms ((x >> 8) + 1/2) 2^-24; Box-Muller.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_API __attribute__((visibility("default")))
+
+/* ------------------------------------------------------------------ */
+/* R2 low-discrepancy sequence, Sec. 3.2 Eq. 6                          */
+/* ------------------------------------------------------------------ */
+
+/* Plastic number psi: the real root of x^3 = x + 1 (Sec. 3.2), found by
+ * Newton's method in binary128 so that 2^64/psi and 2^64/psi^2 can be
+ * rounded to integers exactly. */
+static __float128 plastic_number_q(void) {
+    __float128 x = 1.3Q;
+    for (int it = 0; it < 200; ++it) {
+        __float128 fx = x * x * x - x - 1.0Q;
+        __float128 dfx = 3.0Q * x * x - 1.0Q;
+        __float128 nx = x - fx / dfx;
+        if (nx == x) break;
+        x = nx;
+    }
+    return x;
+}
+
+static uint64_t round_frac_to_u64(__float128 a) {
+    /* a in (0,1): returns round(a * 2^64) */
+    const __float128 two64 = 18446744073709551616.0Q;
+    __float128 v = a * two64 + 0.5Q;
+    /* split to avoid relying on a 128-bit -> u64 conversion near 2^64 */
+    __float128 hi = (__float128)(uint64_t)(v / 4294967296.0Q);
+    __float128 lo = v - hi * 4294967296.0Q;
+    return ((uint64_t)hi << 32) + (uint64_t)lo;
+}
+
+ORACLE_API void oracle_plastic_number(double* psi) { *psi = (double)plastic_number_q(); }
+
+/* increments A_x = round(2^64 / psi), A_y = round(2^64 / psi^2) */
+ORACLE_API void oracle_r2_increments(uint64_t out[2]) {
+    __float128 psi = plastic_number_q();
+    out[0] = round_frac_to_u64(1.0Q / psi);
+    out[1] = round_frac_to_u64(1.0Q / (psi * psi));
+}
+
+/* u_n = frac(s0 + n alpha) for n = index+1 .. index+n_pts, returned in [0,1)
+ * with 53 significant bits (the top 53 bits of the 64-bit state). */
+ORACLE_API void oracle_r2_points(uint64_t s0x, uint64_t s0y, uint64_t index,
+                                 int64_t n_pts, double* ux, double* uy) {
+    uint64_t inc[2];
+    oracle_r2_increments(inc);
+    for (int64_t i = 0; i < n_pts; ++i) {
+        uint64_t n = index + 1u + (uint64_t)i;
+        uint64_t Ux = s0x + n * inc[0];
+        uint64_t Uy = s0y + n * inc[1];
+        ux[i] = (double)(Ux >> 11) * 0x1p-53;
+        uy[i] = (double)(Uy >> 11) * 0x1p-53;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Frequency maps                                                      */
+/* ------------------------------------------------------------------ */
+
+/* Eq. 5 with delta_f_x = delta_f_y = df and n_x = n_y = N (Sec. 3.2):
+ * f = df*N*(u - 1/2).  Each of the K points of a set stands for an equal
+ * share (N df)^2 / K of the square domain (delta_f^2 when K = N^2, Eq. 3). */
+ORACLE_API void oracle_sample_cartesian(uint64_t s0x, uint64_t s0y, uint64_t index,
+                                        int64_t n_sets, int64_t K, int32_t N, double df,
+                                        double* fx, double* fy, double* area) {
+    int64_t n = n_sets * K;
+    double* ux = (double*)malloc(sizeof(double) * (size_t)n);
+    double* uy = (double*)malloc(sizeof(double) * (size_t)n);
+    oracle_r2_points(s0x, s0y, index, n, ux, uy);
+    double L = (double)N * df;
+    for (int64_t i = 0; i < n; ++i) {
+        fx[i] = L * (ux[i] - 0.5);
+        fy[i] = L * (uy[i] - 0.5);
+        area[i] = L * L / (double)K;
+    }
+    free(ux);
+    free(uy);
+}
+
+/* Log-polar map: ln|f| uniform on [ln fmin, ln fmax] from the first R2
+ * coordinate, angle 2 pi u from the second.  The (ln f, theta) box has
+ * measure 2 pi ln(fmax/fmin); its Jacobian to (fx, fy) is |f|^2, so each of
+ * the K points of a set carries area 2 pi ln(fmax/fmin) |f|^2 / K. */
+ORACLE_API void oracle_sample_logpolar(uint64_t s0x, uint64_t s0y, uint64_t index,
+                                       int64_t n_sets, int64_t K, double fmin, double fmax,
+                                       double* fx, double* fy, double* area) {
+    int64_t n = n_sets * K;
+    double* ux = (double*)malloc(sizeof(double) * (size_t)n);
+    double* uy = (double*)malloc(sizeof(double) * (size_t)n);
+    oracle_r2_points(s0x, s0y, index, n, ux, uy);
+    double lr = log(fmax / fmin);
+    for (int64_t i = 0; i < n; ++i) {
+        double f = fmin * exp(lr * ux[i]);
+        double th = 2.0 * M_PI * uy[i];
+        fx[i] = f * cos(th);
+        fy[i] = f * sin(th);
+        area[i] = 2.0 * M_PI * lr * f * f / (double)K;
+    }
+    free(ux);
+    free(uy);
+}
+
+/* ------------------------------------------------------------------ */
+/* Phase PSD and aperture filter, Sec. 4.1 Eq. 7                       */
+/* ------------------------------------------------------------------ */
+
+/* Kolmogorov constant of the phase PSD in cycles/m:
+ * c = Gamma(11/6)^2 / (2 pi^(11/3)) * (24/5 Gamma(6/5))^(5/6); Eq. 7 prints
+ * it rounded to 0.02289. */
+ORACLE_API double oracle_psd_constant(void) {
+    double g = tgamma(11.0 / 6.0);
+    return g * g / (2.0 * pow(M_PI, 11.0 / 3.0)) * pow(24.0 / 5.0 * tgamma(6.0 / 5.0), 5.0 / 6.0);
+}
+
+/* model 0: Kolmogorov c r0^(-5/3) f^(-11/3); model 1: von Karman
+ * c r0^(-5/3) (f^2 + L0^-2)^(-11/6) (first factor of Eq. 7).  An exact
+ * f = 0 has no finite Kolmogorov value and contributes nothing. */
+ORACLE_API double oracle_psd(int32_t model, double c, double r0, double L0, double f) {
+    double inv_L02 = (model == 1) ? 1.0 / (L0 * L0) : 0.0;
+    double q = f * f + inv_L02;
+    if (q == 0.0) return 0.0;
+    return c * pow(r0, -5.0 / 3.0) * pow(q, -11.0 / 6.0);
+}
+
+/* Circular aperture of diameter D with central obstruction d (Eq. 7):
+ * F = 2 (D J1(pi D f) - d J1(pi d f)) / (pi (D^2 - d^2) f), F(0) = 1;
+ * Eq. 7's factor 4(...)^2 is F^2. */
+ORACLE_API double oracle_aperture_filter(double D, double d, double f) {
+    if (f == 0.0) return 1.0;
+    double num = D * j1(M_PI * D * f);
+    if (d > 0.0) num -= d * j1(M_PI * d * f);
+    return 2.0 * num / (M_PI * (D * D - d * d) * f);
+}
+
+/* w_k = sqrt(W(|f_k|) * area_k) [* F(|f_k|)], the amplitude factor of Eq. 3
+ * (sqrt(delta_f_x delta_f_y W)).  has_ap = 0: phase; 1: piston filter. */
+ORACLE_API void oracle_weights(int32_t model, double c, double r0, double L0,
+                               int32_t has_ap, double D, double d, int64_t n,
+                               const double* fx, const double* fy, const double* area,
+                               double* w) {
+    for (int64_t i = 0; i < n; ++i) {
+        double f = sqrt(fx[i] * fx[i] + fy[i] * fy[i]);
+        double v = sqrt(oracle_psd(model, c, r0, L0, f) * area[i]);
+        if (has_ap) v *= oracle_aperture_filter(D, d, f);
+        w[i] = v;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 and Gaussian coefficients                             */
+/* ------------------------------------------------------------------ */
+
+/* Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11): each
+ * round multiplies words 0 and 2 by the two round multipliers, mixes the
+ * high halves with words 1 and 3 and the round key, and bumps the key by
+ * the two Weyl constants (the golden ratio and sqrt(3)-1 in 0.32 fixed
+ * point). */
+ORACLE_API void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                                     uint32_t out[4]) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* one 32-bit word -> uniform in (0,1): the top 24 bits plus half a step */
+static double word_to_uniform(uint32_t x) { return ((double)(x >> 8) + 0.5) * 0x1p-24; }
+
+static void philox_block(uint64_t seed, uint64_t realisation, uint32_t block, uint32_t out[4]) {
+    uint32_t ctr[4] = {block, (uint32_t)realisation, (uint32_t)(realisation >> 32), 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    oracle_philox4x32_10(ctr, key, out);
+}
+
+/* Coefficients of one realisation: c[2k] multiplies cos(2 pi f_k.x),
+ * c[2k+1] multiplies sin(2 pi f_k.x).
+ * mode 0 (Gaussian cos/sin): Philox block t gives four uniforms; Box-Muller
+ *   of (u0,u1) and of (u2,u3) gives c[4t..4t+3].
+ * mode 1 (Eq. 3 literal): block t = k gives R_n = sqrt(-2 ln u0) cos(2 pi u1)
+ *   and R_u = u2; a = sqrt(2) R_n cos(2 pi R_u), b = -sqrt(2) R_n sin(2 pi R_u),
+ *   so a cos + b sin = (2/sqrt 2) R_n cos(2 pi (f.x + R_u)). */
+ORACLE_API void oracle_coefficients(uint64_t seed, uint64_t realisation, int64_t K,
+                                    int32_t mode, double* c) {
+    if (mode == 0) {
+        int64_t nblk = (2 * K + 3) / 4;
+        for (int64_t t = 0; t < nblk; ++t) {
+            uint32_t x[4];
+            philox_block(seed, realisation, (uint32_t)t, x);
+            double g[4];
+            for (int h = 0; h < 2; ++h) {
+                double u1 = word_to_uniform(x[2 * h]);
+                double u2 = word_to_uniform(x[2 * h + 1]);
+                double rho = sqrt(-2.0 * log(u1));
+                g[2 * h] = rho * cos(2.0 * M_PI * u2);
+                g[2 * h + 1] = rho * sin(2.0 * M_PI * u2);
+            }
+            for (int i = 0; i < 4; ++i) {
+                int64_t j = 4 * t + i;
+                if (j < 2 * K) c[j] = g[i];
+            }
+        }
+    } else {
+        for (int64_t k = 0; k < K; ++k) {
+            uint32_t x[4];
+            philox_block(seed, realisation, (uint32_t)k, x);
+            double u1 = word_to_uniform(x[0]);
+            double u2 = word_to_uniform(x[1]);
+            double Rn = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+            double Ru = word_to_uniform(x[2]);
+            c[2 * k] = sqrt(2.0) * Rn * cos(2.0 * M_PI * Ru);
+            c[2 * k + 1] = -sqrt(2.0) * Rn * sin(2.0 * M_PI * Ru);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Direct harmonic sums, Sec. 3 Eq. 3                                   */
+/* ------------------------------------------------------------------ */
+
+/* Realisation r uses frequency set s = r / R_block (fx, fy, w are
+ * [n_sets][K]); its coefficients come from coef[r][2K] when coef is
+ * non-NULL, else from (seed, counter + r).  filt (nullable) is a per
+ * (column, set, frequency) multiplier [n_cols][n_sets][K].
+ * out[r][p] = sum_k w_k filt_pk (c_2k cos 2 pi f_k.x_p + c_2k+1 sin 2 pi f_k.x_p) */
+static void direct_sum(int64_t K, const double* fx, const double* fy, const double* w,
+                       int64_t P, const double* px, const double* py, const double* filt,
+                       int64_t n_sets, int64_t R, int64_t R_block, uint64_t seed,
+                       uint64_t counter, int32_t mode, const double* coef, double* out) {
+#pragma omp parallel
+    {
+        double* c = (double*)malloc(sizeof(double) * (size_t)(2 * K));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t r = 0; r < R; ++r) {
+            int64_t s = r / R_block;
+            const double* cr = c;
+            if (coef) cr = coef + r * 2 * K;
+            else oracle_coefficients(seed, counter + (uint64_t)r, K, mode, c);
+            for (int64_t p = 0; p < P; ++p) {
+                double acc = 0.0;
+                for (int64_t k = 0; k < K; ++k) {
+                    int64_t i = s * K + k;
+                    double arg = 2.0 * M_PI * (fx[i] * px[p] + fy[i] * py[p]);
+                    double amp = w[i];
+                    if (filt) amp *= filt[(p * n_sets + s) * K + k];
+                    acc += amp * (cr[2 * k] * cos(arg) + cr[2 * k + 1] * sin(arg));
+                }
+                out[r * P + p] = acc;
+            }
+        }
+        free(c);
+    }
+}
+
+ORACLE_API void oracle_synthesize(int64_t K, const double* fx, const double* fy, const double* w,
+                                  int64_t P, const double* px, const double* py, int64_t R,
+                                  int64_t R_block, uint64_t seed, uint64_t counter, int32_t mode,
+                                  const double* coef, double* phase) {
+    int64_t n_sets = (R + R_block - 1) / R_block;
+    direct_sum(K, fx, fy, w, P, px, py, NULL, n_sets, R, R_block, seed, counter, mode, coef,
+               phase);
+}
+
+/* Aperture piston (Sec. 4.1): the phase averaged over the aperture is the
+ * harmonic sum with each frequency multiplied by that aperture's filter F
+ * (Eq. 7), evaluated at the aperture centre.  w is the unfiltered phase
+ * weight. */
+ORACLE_API void oracle_piston(int64_t K, const double* fx, const double* fy, const double* w,
+                              int64_t n_ap, const double* cx, const double* cy,
+                              const double* apD, const double* apd, int64_t R, int64_t R_block,
+                              uint64_t seed, uint64_t counter, int32_t mode, const double* coef,
+                              double* piston) {
+    int64_t n_sets = (R + R_block - 1) / R_block;
+    double* filt = (double*)malloc(sizeof(double) * (size_t)(n_ap * n_sets * K));
+    for (int64_t p = 0; p < n_ap; ++p)
+        for (int64_t i = 0; i < n_sets * K; ++i) {
+            double f = sqrt(fx[i] * fx[i] + fy[i] * fy[i]);
+            filt[p * n_sets * K + i] = oracle_aperture_filter(apD[p], apd[p], f);
+        }
+    direct_sum(K, fx, fy, w, n_ap, cx, cy, filt, n_sets, R, R_block, seed, counter, mode, coef,
+               piston);
+    free(filt);
+}
+
+/* Differential-piston structure function over baselines (Sec. 4.4): for
+ * each realisation the pistons of two equal apertures at 0 and at B_b are
+ * formed (w already carries the aperture filter), their difference squared
+ * is averaged over realisations.  sf[b] = mean_r dp^2,
+ * sf_stderr[b] = sqrt(sample variance of dp^2 / R). */
+ORACLE_API void oracle_diff_piston_sf(int64_t K, const double* fx, const double* fy,
+                                      const double* w, int64_t nB, const double* bx,
+                                      const double* by, int64_t R, int64_t R_block,
+                                      uint64_t seed, uint64_t counter, int32_t mode,
+                                      double* sf, double* sf_stderr) {
+    int64_t P = nB + 1;
+    double* px = (double*)malloc(sizeof(double) * (size_t)P);
+    double* py = (double*)malloc(sizeof(double) * (size_t)P);
+    px[0] = 0.0;
+    py[0] = 0.0;
+    for (int64_t b = 0; b < nB; ++b) {
+        px[b + 1] = bx[b];
+        py[b + 1] = by[b];
+    }
+    double* pist = (double*)malloc(sizeof(double) * (size_t)(R * P));
+    int64_t n_sets = (R + R_block - 1) / R_block;
+    direct_sum(K, fx, fy, w, P, px, py, NULL, n_sets, R, R_block, seed, counter, mode, NULL,
+               pist);
+    for (int64_t b = 0; b < nB; ++b) {
+        double s2 = 0.0, s4 = 0.0;
+        for (int64_t r = 0; r < R; ++r) {
+            double dp = pist[r * P + b + 1] - pist[r * P];
+            s2 += dp * dp;
+            s4 += dp * dp * dp * dp;
+        }
+        double mean = s2 / (double)R;
+        sf[b] = mean;
+        if (sf_stderr) {
+            double var = (R > 1) ? (s4 - s2 * s2 / (double)R) / (double)(R - 1) : 0.0;
+            sf_stderr[b] = sqrt(var > 0.0 ? var / (double)R : 0.0);
+        }
+    }
+    free(pist);
+    free(px);
+    free(py);
+}
