@@ -1,0 +1,238 @@
+/*
+ * qrfs.h -- C ABI of libqrfs, quasi-random frequency sampling for optical
+ * turbulence on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Berdja et al., "Quasi-Random Frequency Sampling for Optical
+ * Turbulence Simulations" (arXiv 2404.02978).  A turbulent quantity is the
+ * direct harmonic sum of Sec. 3, Eq. 3 over K spatial frequencies f_k placed
+ * by the R2 low-discrepancy sequence (Sec. 3.2, Eqs. 5-6), each weighted by
+ * sqrt(PSD x cell area) (Eq. 3) and, for aperture piston, by the circular
+ * aperture filter of Sec. 4.1, Eq. 7.  Each frequency carries two random
+ * coefficients:
+ *     phi_r(x) = sum_k w_k [ a_rk cos(2 pi f_k.x) + b_rk sin(2 pi f_k.x) ].
+ *
+ * Conventions for every entry point
+ *   - Units: frequencies in cycles/m, positions in m, phase in rad at the
+ *     wavelength r0 refers to (Sec. 4.1), structure functions in rad^2.
+ *   - Array arguments are DEVICE pointers (memory of the context's device),
+ *     contiguous, naturally aligned, owned by the caller, unless the comment
+ *     says "host".  Struct arguments are host pointers.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL =
+ *     the null stream) and the call returns after enqueueing; results are
+ *     ready when the stream is synchronised.  Calls on one context must not
+ *     overlap in time (the context's workspace is shared).
+ *   - Every argument is checked before anything is enqueued.  On error the
+ *     call returns a negative status, enqueues nothing and leaves a
+ *     thread-local detail message (qrfs_last_error_detail).  No C++
+ *     exception crosses this boundary.
+ *   - Realisations are grouped in frequency sets (R_block realisations per
+ *     set, n_sets = ceil(R / R_block)): realisation r uses set r / R_block.
+ *     R_block = 1 gives every realisation fresh frequencies, as the paper
+ *     does (Sec. 3.2: the sequence is never reinitialised); R_block = R
+ *     shares one set (the static sampling Sec. 2.3 warns about).
+ *   - Random coefficients: Philox4x32-10 keyed by rng.seed, counter
+ *     (block t, realisation lo32, realisation hi32, 0) with realisation =
+ *     rng.counter + r; each 32-bit word gives u = ((x >> 8) + 1/2) 2^-24;
+ *     Box-Muller of (u0,u1) and (u2,u3) gives coefficients c[4t..4t+3] with
+ *     c[2k] = a_k, c[2k+1] = b_k (QRFS_COEF_GAUSS_CS).  QRFS_COEF_EQ3 uses
+ *     block t = k: R_n = sqrt(-2 ln u0) cos(2 pi u1), R_u = u2,
+ *     a = sqrt2 R_n cos(2 pi R_u), b = -sqrt2 R_n sin(2 pi R_u), which is the
+ *     literal (2/sqrt2) R_n cos(2 pi (f.x + R_u)) term of Eq. 3.
+ */
+#ifndef QRFS_H
+#define QRFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define QRFS_API __attribute__((visibility("default")))
+#else
+#define QRFS_API
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef int32_t qrfs_status;
+#define QRFS_OK 0
+#define QRFS_ERR_INVALID_ARG (-1)   /* bad size, pointer, parameter          */
+#define QRFS_ERR_OUT_OF_MEMORY (-2) /* workspace allocation failed            */
+#define QRFS_ERR_DEVICE (-3)        /* HIP runtime error (launch, fault)      */
+#define QRFS_ERR_UNSUPPORTED (-4)   /* valid but not implemented combination  */
+
+#define QRFS_ABI_VERSION 1
+
+/* Static string for a status code. */
+QRFS_API const char* qrfs_error_string(qrfs_status s);
+/* Thread-local detail of the last failing call on this thread ("" if none);
+ * valid until the next library call on the same thread. */
+QRFS_API const char* qrfs_last_error_detail(void);
+/* QRFS_ABI_VERSION of the built library. */
+QRFS_API int32_t qrfs_abi_version(void);
+
+/* --------------------------------------------------------------- context */
+/* Opaque: device ordinal, device workspace (grown on demand, freed by
+ * destroy), tuned launch shapes. */
+typedef struct qrfs_context qrfs_context;
+
+/* Creates a context on HIP device `device`.  *out receives the handle. */
+QRFS_API qrfs_status qrfs_context_create(qrfs_context** out, int32_t device);
+/* Synchronises the device and frees the workspace.  NULL is accepted. */
+QRFS_API qrfs_status qrfs_context_destroy(qrfs_context* ctx);
+
+/* ------------------------------------------------------------ parameters */
+/* Phase PSD (Sec. 4.1, Eq. 7 first factor), cycles/m:
+ *   von Karman  W(f) = c r0^(-5/3) (f^2 + L0^-2)^(-11/6)
+ *   Kolmogorov  W(f) = c r0^(-5/3) f^(-11/3)     (L0 ignored; W(0) := 0)
+ * c <= 0 selects Gamma(11/6)^2/(2 pi^(11/3)) (24/5 Gamma(6/5))^(5/6)
+ * = 0.0228955871..., the value Eq. 7 prints as 0.02289. */
+#define QRFS_PSD_KOLMOGOROV 0
+#define QRFS_PSD_VON_KARMAN 1
+typedef struct {
+    int32_t model;
+    double c;
+    double r0; /* Fried parameter, m (> 0) */
+    double L0; /* outer scale, m (> 0 for von Karman) */
+} qrfs_psd;
+
+/* Circular aperture of diameter D with central obstruction d (Eq. 7):
+ * F(f) = 2 (D J1(pi D f) - d J1(pi d f)) / (pi (D^2 - d^2) f), F(0) = 1,
+ * applied signed (Eq. 7's 4(...)^2 is F^2).  0 <= d < D. */
+typedef struct {
+    double D;
+    double d;
+} qrfs_aperture;
+
+/* Frequency sampler (Sec. 3.2).  The 2-D R2 sequence is kept as the exact
+ * 64-bit Weyl sequence U_n = S0 + n A mod 2^64 with A = round(2^64/psi^j),
+ * psi the plastic number (Eq. 6); u = (U >> 11) 2^-53.  The state is
+ * updated before use, so a call starting at `index` uses n = index+1 ...
+ *   R2_CARTESIAN (Eq. 5, delta_f_x = delta_f_y = df, n_x = n_y = N):
+ *       f = N df (u - 1/2), cell area (N df)^2 / K   (= df^2 for K = N^2);
+ *       N df = 2 max|f|, as the worked example of Sec. 4.4 fixes.
+ *   R2_LOGPOLAR: |f| = fmin (fmax/fmin)^(u_x), angle = 2 pi u_y,
+ *       cell area = 2 pi ln(fmax/fmin) |f|^2 / K.
+ *   LEARNED: reserved (QRFS_ERR_UNSUPPORTED).
+ * seed_x, seed_y: S0 in 0.64 fixed point (2^63 = 1/2, Sec. 3.2's (0.5, 0.5)).
+ * index (IN/OUT): position in the sequence; every call advances it by the
+ * number of points drawn, so consecutive calls continue the sequence. */
+#define QRFS_SAMPLER_R2_CARTESIAN 0
+#define QRFS_SAMPLER_R2_LOGPOLAR 1
+#define QRFS_SAMPLER_LEARNED 2
+typedef struct {
+    int32_t scheme;
+    int32_t N;   /* Cartesian: points per axis of the domain (> 0)   */
+    double df;   /* Cartesian: frequency pitch (> 0)                 */
+    double fmin; /* log-polar: band, 0 < fmin < fmax                 */
+    double fmax;
+    uint64_t seed_x;
+    uint64_t seed_y;
+    uint64_t index;
+} qrfs_sampler;
+
+#define QRFS_COEF_GAUSS_CS 0
+#define QRFS_COEF_EQ3 1
+typedef struct {
+    uint64_t seed;    /* Philox key                                   */
+    uint64_t counter; /* global index of realisation 0 of this call   */
+    int32_t mode;     /* QRFS_COEF_GAUSS_CS or QRFS_COEF_EQ3          */
+} qrfs_rng;
+
+/* Arithmetic of the sums:
+ *   FP64        FP64 range reduction, FP64 sincos, FP64 Box-Muller and
+ *               FP64 accumulation (vector ALU); output double.
+ *   FP32        FP64 range reduction of 2 pi f.x, FP32 sincos and
+ *               Box-Muller, FP32 matrix-core (MFMA) contraction with FP32
+ *               accumulation, promoted to FP64 every 64 frequencies;
+ *               output float.
+ *   SPLIT_BF16  as FP32 but each operand is split into bf16 hi + lo and the
+ *               contraction is hi.hi + hi.lo + lo.hi on bf16 MFMA with FP32
+ *               accumulation; output float. */
+#define QRFS_PREC_FP64 0
+#define QRFS_PREC_FP32 1
+#define QRFS_PREC_SPLIT_BF16 2
+
+/* ---------------------------------------------------------- entry points */
+
+/* R2 frequency sampling (Sec. 3.2, Eqs. 5-6).  Writes n_sets*K points
+ * (set-major: set s occupies [s*K, (s+1)*K)) to fx, fy (cycles/m) and the
+ * cell area each point stands for to area (m^-2), all double[n_sets*K].
+ * Cell areas are per set of K points.  s->index += n_sets*K on success.
+ * Errors: K, n_sets <= 0; NULL pointers; Cartesian N <= 0 or df <= 0;
+ * log-polar fmin <= 0 or fmax <= fmin; LEARNED -> QRFS_ERR_UNSUPPORTED. */
+QRFS_API qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s, int64_t n_sets,
+                                    int64_t K, double* fx, double* fy, double* area,
+                                    void* stream);
+
+/* Amplitude weights of Eq. 3: w = sqrt(W(|f|) area) (phase), multiplied by
+ * the signed aperture filter F(|f|) when ap != NULL (piston of equal
+ * apertures, Eq. 7).  All arrays double[n].  An exact f = 0 with the
+ * Kolmogorov model contributes w = 0.
+ * Errors: n <= 0; NULL arrays; r0 <= 0; von Karman L0 <= 0; unknown model;
+ * ap with D <= 0, d < 0 or d >= D. */
+QRFS_API qrfs_status qrfs_weights(qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aperture* ap,
+                         int64_t n, const double* fx, const double* fy, const double* area,
+                         double* w, void* stream);
+
+/* Phase field, Eq. 3: phase[r][p] = phi_r(px[p], py[p]) for r < R, p < P.
+ * fx, fy, w: double[n_sets][K] (n_sets = ceil(R/R_block)); px, py:
+ * double[P]; coef: NULL to draw the coefficients with rng (rng then
+ * required), or double[R][2K] (c[2k] = a, c[2k+1] = b) supplied by the
+ * caller (rng ignored).  phase: double[R][P] for QRFS_PREC_FP64, float[R][P]
+ * otherwise (row-major).
+ * Errors: K, P, R <= 0; R_block outside [1, R]; NULL arrays; unknown
+ * precision; rng NULL with coef NULL; unknown coefficient mode. */
+QRFS_API qrfs_status qrfs_synthesize_phase(qrfs_context* ctx, int64_t K, const double* fx,
+                                  const double* fy, const double* w, int64_t P,
+                                  const double* px, const double* py, int64_t R,
+                                  int64_t R_block, const qrfs_rng* rng, const double* coef,
+                                  int32_t precision, void* phase, void* stream);
+
+/* Aperture pistons (Sec. 4.1): the phase averaged over aperture j (centre
+ * cx[j], cy[j], diameters apD[j] > apd[j] >= 0) equals the harmonic sum with
+ * each frequency multiplied by that aperture's filter F (Eq. 7), evaluated
+ * at the centre.  w is the UNFILTERED phase weight.  piston: [R][n_ap],
+ * double for FP64, float otherwise.  Other arguments as
+ * qrfs_synthesize_phase.  Extra errors: n_ap <= 0; NULL apD/apd. */
+QRFS_API qrfs_status qrfs_piston(qrfs_context* ctx, int64_t K, const double* fx, const double* fy,
+                        const double* w, int64_t n_ap, const double* cx, const double* cy,
+                        const double* apD, const double* apd, int64_t R, int64_t R_block,
+                        const qrfs_rng* rng, const double* coef, int32_t precision,
+                        void* piston, void* stream);
+
+/* Differential pistons between two equal apertures, one at the origin and
+ * one at baseline b (Sec. 4.4): dp[r][b] = p_r(bx[b], by[b]) - p_r(0, 0),
+ * evaluated directly as sum_k w_k [a (cos 2 pi f.B - 1) + b sin 2 pi f.B].
+ * w must already carry the aperture filter (qrfs_weights with ap).
+ * dp: [R][nB], double for FP64, float otherwise.  Other arguments and
+ * errors as qrfs_synthesize_phase, with bx, by: double[nB] (device). */
+QRFS_API qrfs_status qrfs_diff_piston(qrfs_context* ctx, int64_t K, const double* fx, const double* fy,
+                             const double* w, int64_t nB, const double* bx, const double* by,
+                             int64_t R, int64_t R_block, const qrfs_rng* rng, const double* coef,
+                             int32_t precision, void* dp, void* stream);
+
+/* Differential-piston structure function (Sec. 4.4), end to end: draws
+ * ceil(R/R_block) frequency sets of K points with the sampler (advancing
+ * s->index by n_sets*K), weights them with the PSD and the aperture filter,
+ * draws the coefficients with rng and returns, per baseline b,
+ *   sf[b]        = (1/R) sum_r dp_rb^2                       (rad^2)
+ *   sf_stderr[b] = sqrt( (sum dp^4 - (sum dp^2)^2 / R) / ((R-1) R) )
+ * (the standard error of sf, NULL to skip).  dp never reaches memory; the
+ * sums are accumulated in FP64 and reduced in a fixed order, so results are
+ * bit-reproducible.  sf, sf_stderr: double[nB] (device).  bx, by: double[nB]
+ * (device).  Errors: as qrfs_sample_frequencies, qrfs_weights (ap required)
+ * and qrfs_synthesize_phase. */
+QRFS_API qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
+                                       const qrfs_aperture* ap, int64_t nB, const double* bx,
+                                       const double* by, qrfs_sampler* s, int64_t K, int64_t R,
+                                       int64_t R_block, const qrfs_rng* rng, int32_t precision,
+                                       double* sf, double* sf_stderr, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QRFS_H */

@@ -25,7 +25,8 @@
  *     (one normal amplitude, one uniform phase, factor 2/sqrt 2) is mode 1.
  *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the
  *     64-bit seed, counter (block, realisation lo, realisation hi, 0);
- *     uniforms ((x >> 8) + 1/2) 2^-24; Box-Muller.
+ *     uniforms ((x >> 9) + 1/2) 2^-23 (exactly representable in binary32
+ *     as well as binary64); Box-Muller.
  */
 #include <math.h>
 #include <stdint.h>
@@ -209,8 +210,9 @@ ORACLE_API void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t ke
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* one 32-bit word -> uniform in (0,1): the top 24 bits plus half a step */
-static double word_to_uniform(uint32_t x) { return ((double)(x >> 8) + 0.5) * 0x1p-24; }
+/* one 32-bit word -> uniform in (0,1): the top 23 bits plus half a step,
+ * (2m + 1) 2^-24 with 2m + 1 < 2^24, so the value is exact in binary32 */
+static double word_to_uniform(uint32_t x) { return ((double)(x >> 9) + 0.5) * 0x1p-23; }
 
 static void philox_block(uint64_t seed, uint64_t realisation, uint32_t block, uint32_t out[4]) {
     uint32_t ctr[4] = {block, (uint32_t)realisation, (uint32_t)(realisation >> 32), 0u};

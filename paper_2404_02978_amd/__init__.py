@@ -1,0 +1,260 @@
+"""Python binding of libqrfs: quasi-random frequency sampling for optical
+turbulence (arXiv 2404.02978) on AMD Instinct MI355X (gfx950).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libqrfs.so``; torch provides device memory and the current stream.
+The functions mirror the C ABI in ``include/qrfs.h`` (same names without the
+``qrfs_`` prefix).  If the library is missing or no GPU is present, calls
+raise immediately; there is no CPU fallback.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqrfs.so")
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_OUT_OF_MEMORY = -2
+ERR_DEVICE = -3
+ERR_UNSUPPORTED = -4
+
+PSD_KOLMOGOROV = 0
+PSD_VON_KARMAN = 1
+SAMPLER_R2_CARTESIAN = 0
+SAMPLER_R2_LOGPOLAR = 1
+SAMPLER_LEARNED = 2
+COEF_GAUSS_CS = 0
+COEF_EQ3 = 1
+PREC_FP64 = 0
+PREC_FP32 = 1
+PREC_SPLIT_BF16 = 2
+SEED_HALF = 1 << 63
+
+
+class QrfsError(RuntimeError):
+    def __init__(self, status, detail):
+        super().__init__(f"qrfs status {status}: {detail}")
+        self.status = status
+        self.detail = detail
+
+
+class Psd(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("c", ctypes.c_double), ("r0", ctypes.c_double),
+                ("L0", ctypes.c_double)]
+
+
+class Aperture(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_double), ("d", ctypes.c_double)]
+
+
+class Sampler(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("N", ctypes.c_int32), ("df", ctypes.c_double),
+                ("fmin", ctypes.c_double), ("fmax", ctypes.c_double),
+                ("seed_x", ctypes.c_uint64), ("seed_y", ctypes.c_uint64),
+                ("index", ctypes.c_uint64)]
+
+
+class Rng(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("counter", ctypes.c_uint64), ("mode", ctypes.c_int32)]
+
+
+def psd(r0, L0=None, model=None, c=0.0):
+    if model is None:
+        model = PSD_KOLMOGOROV if L0 is None else PSD_VON_KARMAN
+    return Psd(model, c, r0, 0.0 if L0 is None else L0)
+
+
+def logpolar_sampler(fmin, fmax, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
+    return Sampler(SAMPLER_R2_LOGPOLAR, 0, 0.0, fmin, fmax, seed_x, seed_y, index)
+
+
+def cartesian_sampler(N, df, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
+    return Sampler(SAMPLER_R2_CARTESIAN, N, df, 0.0, 0.0, seed_x, seed_y, index)
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+
+
+def load_library():
+    """Loads libqrfs.so (built by ``paper_2404_02978_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2404_02978_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    S = ctypes.c_int32
+    sig = {
+        "qrfs_error_string": (ctypes.c_char_p, [S]),
+        "qrfs_last_error_detail": (ctypes.c_char_p, []),
+        "qrfs_abi_version": (ctypes.c_int32, []),
+        "qrfs_context_create": (S, [ctypes.POINTER(_P), _I32]),
+        "qrfs_context_destroy": (S, [_P]),
+        "qrfs_sample_frequencies": (S, [_P, ctypes.POINTER(Sampler), _I64, _I64, _P, _P, _P, _P]),
+        "qrfs_weights": (S, [_P, ctypes.POINTER(Psd), ctypes.POINTER(Aperture), _I64, _P, _P, _P,
+                             _P, _P]),
+        "qrfs_synthesize_phase": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _I64, _I64,
+                                      ctypes.POINTER(Rng), _P, _I32, _P, _P]),
+        "qrfs_piston": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _I64,
+                            ctypes.POINTER(Rng), _P, _I32, _P, _P]),
+        "qrfs_diff_piston": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _I64, _I64,
+                                 ctypes.POINTER(Rng), _P, _I32, _P, _P]),
+        "qrfs_diff_piston_structure": (S, [_P, ctypes.POINTER(Psd), ctypes.POINTER(Aperture), _I64,
+                                           _P, _P, ctypes.POINTER(Sampler), _I64, _I64, _I64,
+                                           ctypes.POINTER(Rng), _I32, _P, _P, _P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != OK:
+        lib = load_library()
+        raise QrfsError(status, lib.qrfs_last_error_detail().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(t, name, n=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owns a libqrfs context (device workspace) on one HIP device."""
+
+    def __init__(self, device=0):
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: libqrfs needs an MI355X")
+        self.device = torch.device("cuda", device)
+        h = _P()
+        _check(lib.qrfs_context_create(ctypes.byref(h), device))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().qrfs_context_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---------------------------------------------------------------- API
+    def sample_frequencies(self, sampler, n_sets, K):
+        """R2 sampling (Sec. 3.2); returns (fx, fy, area) float64 [n_sets*K];
+        advances sampler.index."""
+        n = n_sets * K
+        fx = torch.empty(n, dtype=torch.float64, device=self.device)
+        fy = torch.empty_like(fx)
+        area = torch.empty_like(fx)
+        _check(load_library().qrfs_sample_frequencies(self._h, ctypes.byref(sampler), n_sets, K,
+                                                      _ptr(fx), _ptr(fy), _ptr(area), _stream()))
+        return fx, fy, area
+
+    def weights(self, psd_, fx, fy, area, aperture=None):
+        n = fx.numel()
+        w = torch.empty(n, dtype=torch.float64, device=self.device)
+        ap = ctypes.byref(aperture) if aperture is not None else None
+        _check(load_library().qrfs_weights(self._h, ctypes.byref(psd_), ap, n,
+                                           _dev_f64(fx, "fx"), _dev_f64(fy, "fy", n),
+                                           _dev_f64(area, "area", n), _ptr(w), _stream()))
+        return w
+
+    def _out(self, R, P, precision):
+        dt = torch.float64 if precision == PREC_FP64 else torch.float32
+        return torch.empty((R, P), dtype=dt, device=self.device)
+
+    @staticmethod
+    def _rng(rng, coef):
+        if coef is not None:
+            return None
+        return ctypes.byref(rng if rng is not None else Rng(0, 0, COEF_GAUSS_CS))
+
+    def synthesize_phase(self, K, fx, fy, w, px, py, R, R_block, rng=None, coef=None,
+                         precision=PREC_FP32, out=None):
+        n_sets = math.ceil(R / R_block)
+        P = px.numel()
+        out = self._out(R, P, precision) if out is None else out
+        _check(load_library().qrfs_synthesize_phase(
+            self._h, K, _dev_f64(fx, "fx", n_sets * K), _dev_f64(fy, "fy", n_sets * K),
+            _dev_f64(w, "w", n_sets * K), P, _dev_f64(px, "px"), _dev_f64(py, "py", P), R, R_block,
+            self._rng(rng, coef), None if coef is None else _dev_f64(coef, "coef", R * 2 * K),
+            precision, _ptr(out), _stream()))
+        return out
+
+    def piston(self, K, fx, fy, w, cx, cy, apD, apd, R, R_block, rng=None, coef=None,
+               precision=PREC_FP32, out=None):
+        n_sets = math.ceil(R / R_block)
+        n_ap = cx.numel()
+        out = self._out(R, n_ap, precision) if out is None else out
+        _check(load_library().qrfs_piston(
+            self._h, K, _dev_f64(fx, "fx", n_sets * K), _dev_f64(fy, "fy", n_sets * K),
+            _dev_f64(w, "w", n_sets * K), n_ap, _dev_f64(cx, "cx"), _dev_f64(cy, "cy", n_ap),
+            _dev_f64(apD, "apD", n_ap), _dev_f64(apd, "apd", n_ap), R, R_block,
+            self._rng(rng, coef), None if coef is None else _dev_f64(coef, "coef", R * 2 * K),
+            precision, _ptr(out), _stream()))
+        return out
+
+    def diff_piston(self, K, fx, fy, w, bx, by, R, R_block, rng=None, coef=None,
+                    precision=PREC_FP32, out=None):
+        n_sets = math.ceil(R / R_block)
+        nB = bx.numel()
+        out = self._out(R, nB, precision) if out is None else out
+        _check(load_library().qrfs_diff_piston(
+            self._h, K, _dev_f64(fx, "fx", n_sets * K), _dev_f64(fy, "fy", n_sets * K),
+            _dev_f64(w, "w", n_sets * K), nB, _dev_f64(bx, "bx"), _dev_f64(by, "by", nB), R,
+            R_block, self._rng(rng, coef),
+            None if coef is None else _dev_f64(coef, "coef", R * 2 * K), precision, _ptr(out),
+            _stream()))
+        return out
+
+    def diff_piston_structure(self, psd_, aperture, bx, by, sampler, K, R, R_block, rng=None,
+                              precision=PREC_FP32, with_stderr=True):
+        """End-to-end differential-piston structure function (Sec. 4.4).
+        Returns (sf, stderr) float64 [nB] on the device; advances sampler.index."""
+        nB = bx.numel()
+        sf = torch.empty(nB, dtype=torch.float64, device=self.device)
+        se = torch.empty_like(sf) if with_stderr else None
+        rng = rng if rng is not None else Rng(0, 0, COEF_GAUSS_CS)
+        _check(load_library().qrfs_diff_piston_structure(
+            self._h, ctypes.byref(psd_), ctypes.byref(aperture), nB, _dev_f64(bx, "bx"),
+            _dev_f64(by, "by", nB), ctypes.byref(sampler), K, R, R_block, ctypes.byref(rng),
+            precision, _ptr(sf), _ptr(se), _stream()))
+        return sf, se

@@ -1,0 +1,416 @@
+// qrfs_api.cpp -- the C ABI of libqrfs: argument checks, the context and
+// its device workspace, and the host-side orchestration of the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "qrfs.h"
+#include "qrfs_internal.hpp"
+
+struct qrfs_context {
+    int device = 0;
+    void* ws = nullptr;
+    size_t ws_size = 0;
+};
+
+namespace {
+
+thread_local std::string g_detail;
+
+qrfs_status fail(qrfs_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_detail = buf;
+    return s;
+}
+
+qrfs_status ok() {
+    g_detail.clear();
+    return QRFS_OK;
+}
+
+// Makes ctx->device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool okay = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        okay = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+qrfs_status hip_fail(hipError_t e, const char* what) {
+    return fail(QRFS_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+
+#define CHECK_PTR(p)                                                                 \
+    do {                                                                             \
+        if ((p) == nullptr) return fail(QRFS_ERR_INVALID_ARG, "%s is NULL", #p);     \
+        if (!aligned8(p)) return fail(QRFS_ERR_INVALID_ARG, "%s is not 8-byte aligned", #p); \
+    } while (0)
+
+qrfs_status ensure_workspace(qrfs_context* ctx, size_t bytes) {
+    if (bytes <= ctx->ws_size) return QRFS_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before workspace growth");
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_size = 0;
+    size_t sz = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
+    e = hipMalloc(&ctx->ws, sz);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(QRFS_ERR_OUT_OF_MEMORY, "workspace of %zu bytes: %s", sz, hipGetErrorString(e));
+    }
+    ctx->ws_size = sz;
+    return QRFS_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+qrfs_status check_psd(const qrfs_psd* psd) {
+    if (!psd) return fail(QRFS_ERR_INVALID_ARG, "psd is NULL");
+    if (psd->model != QRFS_PSD_KOLMOGOROV && psd->model != QRFS_PSD_VON_KARMAN)
+        return fail(QRFS_ERR_INVALID_ARG, "unknown PSD model %d", psd->model);
+    if (!(psd->r0 > 0.0) || !std::isfinite(psd->r0))
+        return fail(QRFS_ERR_INVALID_ARG, "r0 must be > 0 (got %g)", psd->r0);
+    if (psd->model == QRFS_PSD_VON_KARMAN && (!(psd->L0 > 0.0) || !std::isfinite(psd->L0)))
+        return fail(QRFS_ERR_INVALID_ARG, "von Karman L0 must be > 0 (got %g)", psd->L0);
+    if (!std::isfinite(psd->c)) return fail(QRFS_ERR_INVALID_ARG, "PSD constant is not finite");
+    return QRFS_OK;
+}
+
+qrfs_status check_ap(const qrfs_aperture* ap) {
+    if (!(ap->D > 0.0) || !std::isfinite(ap->D))
+        return fail(QRFS_ERR_INVALID_ARG, "aperture D must be > 0 (got %g)", ap->D);
+    if (!(ap->d >= 0.0) || !(ap->d < ap->D))
+        return fail(QRFS_ERR_INVALID_ARG, "obstruction d must satisfy 0 <= d < D (got %g, D=%g)",
+                    ap->d, ap->D);
+    return QRFS_OK;
+}
+
+qrfs_status check_sampler(const qrfs_sampler* s) {
+    if (!s) return fail(QRFS_ERR_INVALID_ARG, "sampler is NULL");
+    if (s->scheme == QRFS_SAMPLER_LEARNED)
+        return fail(QRFS_ERR_UNSUPPORTED, "learned sampler is not available in this build");
+    if (s->scheme == QRFS_SAMPLER_R2_CARTESIAN) {
+        if (s->N <= 0) return fail(QRFS_ERR_INVALID_ARG, "Cartesian N must be > 0 (got %d)", s->N);
+        if (!(s->df > 0.0) || !std::isfinite(s->df))
+            return fail(QRFS_ERR_INVALID_ARG, "Cartesian df must be > 0 (got %g)", s->df);
+    } else if (s->scheme == QRFS_SAMPLER_R2_LOGPOLAR) {
+        if (!(s->fmin > 0.0) || !(s->fmax > s->fmin) || !std::isfinite(s->fmax))
+            return fail(QRFS_ERR_INVALID_ARG, "log-polar band needs 0 < fmin < fmax (got %g, %g)",
+                        s->fmin, s->fmax);
+    } else {
+        return fail(QRFS_ERR_INVALID_ARG, "unknown sampler scheme %d", s->scheme);
+    }
+    return QRFS_OK;
+}
+
+qrfs_status check_sum_common(int64_t K, int64_t P, int64_t R, int64_t R_block,
+                             const qrfs_rng* rng, const double* coef, int32_t precision) {
+    if (K <= 0) return fail(QRFS_ERR_INVALID_ARG, "K must be > 0 (got %lld)", (long long)K);
+    if (P <= 0) return fail(QRFS_ERR_INVALID_ARG, "number of points must be > 0 (got %lld)", (long long)P);
+    if (R <= 0) return fail(QRFS_ERR_INVALID_ARG, "R must be > 0 (got %lld)", (long long)R);
+    if (R_block < 1 || R_block > R)
+        return fail(QRFS_ERR_INVALID_ARG, "R_block must be in [1, R] (got %lld, R=%lld)",
+                    (long long)R_block, (long long)R);
+    if (K > ((int64_t)1 << 33))
+        return fail(QRFS_ERR_INVALID_ARG, "K too large for the 32-bit Philox block counter");
+    if (precision != QRFS_PREC_FP64 && precision != QRFS_PREC_FP32 &&
+        precision != QRFS_PREC_SPLIT_BF16)
+        return fail(QRFS_ERR_INVALID_ARG, "unknown precision %d", precision);
+    if (!coef) {
+        if (!rng) return fail(QRFS_ERR_INVALID_ARG, "rng is NULL and no coefficients were given");
+        if (rng->mode != QRFS_COEF_GAUSS_CS && rng->mode != QRFS_COEF_EQ3)
+            return fail(QRFS_ERR_INVALID_ARG, "unknown coefficient mode %d", rng->mode);
+    } else if (!aligned8(coef)) {
+        return fail(QRFS_ERR_INVALID_ARG, "coef is not 8-byte aligned");
+    }
+    return QRFS_OK;
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Runs launch_sum over all sets, splitting the grid so no launch exceeds
+// 2^30 blocks.
+qrfs_status run_sum(int precision, int basis, int epi, qrfs::SumArgs a, int64_t n_sets,
+                    hipStream_t st) {
+    int64_t rts = qrfs::sum_row_tiles_per_set(precision, basis, a.R_block, a.P);
+    int64_t cts = cdiv(a.P, 32);
+    int64_t per_set = rts * cts;
+    int64_t max_sets = ((int64_t)1 << 30) / (per_set > 0 ? per_set : 1);
+    if (max_sets < 1) return fail(QRFS_ERR_INVALID_ARG, "problem too large for one set");
+    const double* fx0 = a.fx;
+    const double* fy0 = a.fy;
+    const double* w0 = a.w;
+    double* part0 = a.partial;
+    for (int64_t s0 = 0; s0 < n_sets; s0 += max_sets) {
+        int64_t s1 = s0 + max_sets < n_sets ? s0 + max_sets : n_sets;
+        a.set0 = s0;
+        a.set1 = s1;
+        a.fx = fx0 + s0 * a.K;
+        a.fy = fy0 + s0 * a.K;
+        a.w = w0 + s0 * a.K;
+        if (part0) a.partial = part0 + s0 * rts * a.P * 2;
+        hipError_t e = qrfs::launch_sum(precision, basis, epi, a, st);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    }
+    return QRFS_OK;
+}
+
+qrfs_status sum_entry(qrfs_context* ctx, int basis, int64_t K, const double* fx,
+                      const double* fy, const double* w, int64_t P, const double* px,
+                      const double* py, const double* apD, const double* apd, int64_t R,
+                      int64_t R_block, const qrfs_rng* rng, const double* coef,
+                      int32_t precision, void* out, void* stream) {
+    qrfs_status s = check_sum_common(K, P, R, R_block, rng, coef, precision);
+    if (s) return s;
+    CHECK_PTR(fx);
+    CHECK_PTR(fy);
+    CHECK_PTR(w);
+    CHECK_PTR(px);
+    CHECK_PTR(py);
+    if (basis == qrfs::BASIS_PISTON) {
+        CHECK_PTR(apD);
+        CHECK_PTR(apd);
+    }
+    if (!out) return fail(QRFS_ERR_INVALID_ARG, "output is NULL");
+    if (((uintptr_t)out & (precision == QRFS_PREC_FP64 ? 7u : 3u)) != 0)
+        return fail(QRFS_ERR_INVALID_ARG, "output is misaligned");
+    if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
+    qrfs::SumArgs a{};
+    a.K = K;
+    a.fx = fx;
+    a.fy = fy;
+    a.w = w;
+    a.P = P;
+    a.px = px;
+    a.py = py;
+    a.apD = apD;
+    a.apd = apd;
+    a.R = R;
+    a.R_block = R_block;
+    a.seed = rng ? rng->seed : 0;
+    a.counter = rng ? rng->counter : 0;
+    a.mode = rng ? rng->mode : 0;
+    a.coef = coef;
+    a.out = out;
+    a.partial = nullptr;
+    s = run_sum(precision, basis, qrfs::EPI_STORE, a, cdiv(R, R_block), (hipStream_t)stream);
+    if (s) return s;
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qrfs_error_string(qrfs_status s) {
+    switch (s) {
+        case QRFS_OK: return "success";
+        case QRFS_ERR_INVALID_ARG: return "invalid argument";
+        case QRFS_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case QRFS_ERR_DEVICE: return "device (HIP runtime) error";
+        case QRFS_ERR_UNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+const char* qrfs_last_error_detail(void) { return g_detail.c_str(); }
+
+int32_t qrfs_abi_version(void) { return QRFS_ABI_VERSION; }
+
+qrfs_status qrfs_context_create(qrfs_context** out, int32_t device) {
+    if (!out) return fail(QRFS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= n)
+        return fail(QRFS_ERR_INVALID_ARG, "device %d out of range (%d devices)", device, n);
+    qrfs_context* c = new (std::nothrow) qrfs_context();
+    if (!c) return fail(QRFS_ERR_OUT_OF_MEMORY, "host allocation of the context");
+    c->device = device;
+    *out = c;
+    return ok();
+}
+
+qrfs_status qrfs_context_destroy(qrfs_context* ctx) {
+    if (!ctx) return ok();
+    qrfs_status st = QRFS_OK;
+    {
+        DeviceGuard g(ctx->device);
+        if (ctx->ws) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize in destroy");
+            (void)hipFree(ctx->ws);
+        }
+    }
+    delete ctx;
+    return st ? st : ok();
+}
+
+qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s, int64_t n_sets,
+                                    int64_t K, double* fx, double* fy, double* area,
+                                    void* stream) {
+    qrfs_status st = check_sampler(s);
+    if (st) return st;
+    if (K <= 0 || n_sets <= 0)
+        return fail(QRFS_ERR_INVALID_ARG, "K and n_sets must be > 0 (got %lld, %lld)",
+                    (long long)K, (long long)n_sets);
+    if (n_sets > INT64_MAX / K || n_sets * K > ((int64_t)1 << 40))
+        return fail(QRFS_ERR_INVALID_ARG, "n_sets * K too large");
+    CHECK_PTR(fx);
+    CHECK_PTR(fy);
+    CHECK_PTR(area);
+    if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
+    hipError_t e = qrfs::launch_sample(s->scheme, s->seed_x, s->seed_y, s->index, n_sets, K, s->N,
+                                       s->df, s->fmin, s->fmax, fx, fy, area, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sampler launch");
+    s->index += (uint64_t)(n_sets * K);
+    return ok();
+}
+
+qrfs_status qrfs_weights(qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aperture* ap,
+                         int64_t n, const double* fx, const double* fy, const double* area,
+                         double* w, void* stream) {
+    qrfs_status st = check_psd(psd);
+    if (st) return st;
+    if (ap && (st = check_ap(ap))) return st;
+    if (n <= 0) return fail(QRFS_ERR_INVALID_ARG, "n must be > 0 (got %lld)", (long long)n);
+    CHECK_PTR(fx);
+    CHECK_PTR(fy);
+    CHECK_PTR(area);
+    CHECK_PTR(w);
+    if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
+    double c = psd->c > 0.0 ? psd->c : qrfs::kPsdConstant;
+    hipError_t e = qrfs::launch_weights(psd->model, c, psd->r0, psd->L0, ap ? 1 : 0,
+                                        ap ? ap->D : 0.0, ap ? ap->d : 0.0, n, fx, fy, area, w,
+                                        (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "weights launch");
+    return ok();
+}
+
+qrfs_status qrfs_synthesize_phase(qrfs_context* ctx, int64_t K, const double* fx,
+                                  const double* fy, const double* w, int64_t P,
+                                  const double* px, const double* py, int64_t R,
+                                  int64_t R_block, const qrfs_rng* rng, const double* coef,
+                                  int32_t precision, void* phase, void* stream) {
+    return sum_entry(ctx, qrfs::BASIS_PHASE, K, fx, fy, w, P, px, py, nullptr, nullptr, R,
+                     R_block, rng, coef, precision, phase, stream);
+}
+
+qrfs_status qrfs_piston(qrfs_context* ctx, int64_t K, const double* fx, const double* fy,
+                        const double* w, int64_t n_ap, const double* cx, const double* cy,
+                        const double* apD, const double* apd, int64_t R, int64_t R_block,
+                        const qrfs_rng* rng, const double* coef, int32_t precision,
+                        void* piston, void* stream) {
+    return sum_entry(ctx, qrfs::BASIS_PISTON, K, fx, fy, w, n_ap, cx, cy, apD, apd, R, R_block,
+                     rng, coef, precision, piston, stream);
+}
+
+qrfs_status qrfs_diff_piston(qrfs_context* ctx, int64_t K, const double* fx, const double* fy,
+                             const double* w, int64_t nB, const double* bx, const double* by,
+                             int64_t R, int64_t R_block, const qrfs_rng* rng, const double* coef,
+                             int32_t precision, void* dp, void* stream) {
+    return sum_entry(ctx, qrfs::BASIS_DIFF, K, fx, fy, w, nB, bx, by, nullptr, nullptr, R,
+                     R_block, rng, coef, precision, dp, stream);
+}
+
+qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
+                                       const qrfs_aperture* ap, int64_t nB, const double* bx,
+                                       const double* by, qrfs_sampler* s, int64_t K, int64_t R,
+                                       int64_t R_block, const qrfs_rng* rng, int32_t precision,
+                                       double* sf, double* sf_stderr, void* stream) {
+    qrfs_status st = check_psd(psd);
+    if (st) return st;
+    if (!ap) return fail(QRFS_ERR_INVALID_ARG, "aperture is required");
+    if ((st = check_ap(ap))) return st;
+    if ((st = check_sampler(s))) return st;
+    if ((st = check_sum_common(K, nB, R, R_block, rng, nullptr, precision))) return st;
+    CHECK_PTR(bx);
+    CHECK_PTR(by);
+    CHECK_PTR(sf);
+    if (sf_stderr && !aligned8(sf_stderr))
+        return fail(QRFS_ERR_INVALID_ARG, "sf_stderr is not 8-byte aligned");
+    if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
+
+    const int64_t n_sets = cdiv(R, R_block);
+    const int64_t rts = qrfs::sum_row_tiles_per_set(precision, qrfs::BASIS_DIFF, R_block, nB);
+    const size_t partial_bytes = align256((size_t)(n_sets * rts * nB) * 2 * sizeof(double));
+    const size_t per_set = (size_t)K * 4 * sizeof(double);
+    const size_t budget = (size_t)1 << 30;
+    int64_t spb = (int64_t)(budget / per_set);
+    if (spb < 1) spb = 1;
+    if (spb > n_sets) spb = n_sets;
+    const size_t arr = align256((size_t)spb * K * sizeof(double));
+    if ((st = ensure_workspace(ctx, partial_bytes + 4 * arr))) return st;
+    char* base = (char*)ctx->ws;
+    double* partial = (double*)base;
+    double* fx = (double*)(base + partial_bytes);
+    double* fy = (double*)(base + partial_bytes + arr);
+    double* area = (double*)(base + partial_bytes + 2 * arr);
+    double* w = (double*)(base + partial_bytes + 3 * arr);
+    hipStream_t stream_ = (hipStream_t)stream;
+    const double c = psd->c > 0.0 ? psd->c : qrfs::kPsdConstant;
+
+    for (int64_t s0 = 0; s0 < n_sets; s0 += spb) {
+        int64_t s1 = s0 + spb < n_sets ? s0 + spb : n_sets;
+        int64_t ns = s1 - s0;
+        hipError_t e = qrfs::launch_sample(s->scheme, s->seed_x, s->seed_y,
+                                           s->index + (uint64_t)(s0 * K), ns, K, s->N, s->df,
+                                           s->fmin, s->fmax, fx, fy, area, stream_);
+        if (e != hipSuccess) return hip_fail(e, "sampler launch");
+        e = qrfs::launch_weights(psd->model, c, psd->r0, psd->L0, 1, ap->D, ap->d, ns * K, fx, fy,
+                                 area, w, stream_);
+        if (e != hipSuccess) return hip_fail(e, "weights launch");
+        qrfs::SumArgs a{};
+        a.K = K;
+        a.fx = fx;
+        a.fy = fy;
+        a.w = w;
+        a.P = nB;
+        a.px = bx;
+        a.py = by;
+        a.R = R;
+        a.R_block = R_block;
+        a.seed = rng->seed;
+        a.counter = rng->counter;
+        a.mode = rng->mode;
+        a.coef = nullptr;
+        a.out = nullptr;
+        // absolute set bounds; the batch buffers hold exactly these sets
+        a.set0 = s0;
+        a.set1 = s1;
+        a.partial = partial + s0 * rts * nB * 2;
+        e = qrfs::launch_sum(precision, qrfs::BASIS_DIFF, qrfs::EPI_SFSUM, a, stream_);
+        if (e != hipSuccess) return hip_fail(e, "structure-function launch");
+    }
+    hipError_t e = qrfs::launch_reduce_sf(partial, n_sets * rts, nB, R, sf, sf_stderr, stream_);
+    if (e != hipSuccess) return hip_fail(e, "reduction launch");
+    s->index += (uint64_t)(n_sets * K);
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,169 @@
+// qrfs_device.hpp -- device-side building blocks of the quasi-random
+// frequency sampling path (arXiv 2404.02978) for gfx950.
+//
+// Everything here is written for CDNA4 directly: 64-lane wavefronts, the
+// revolution-domain hardware sine/cosine (v_sin_f32 / v_cos_f32 take x and
+// return sin(2 pi x)), FP64 vector arithmetic at full rate, and the
+// 32x32 MFMA operand layouts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qrfs {
+
+// ---------------------------------------------------------------- R2 ----
+// Weyl increments of the 2-D R2 sequence (Sec. 3.2, Eq. 6):
+// round(2^64 / psi) and round(2^64 / psi^2), psi = 1.3247179572447460...
+// the real root of x^3 = x + 1.
+constexpr uint64_t kR2IncX = 0xC13FA9A902A6328FULL;
+constexpr uint64_t kR2IncY = 0x91E10DA5C79E7B1DULL;
+
+// Point n (n >= 1) of the sequence started at (s0x, s0y) in 0.64 fixed
+// point, as doubles in [0,1) carrying the top 53 bits.
+__device__ __forceinline__ void r2_point(uint64_t s0x, uint64_t s0y, uint64_t n, double& ux,
+                                         double& uy) {
+    uint64_t Ux = s0x + n * kR2IncX;
+    uint64_t Uy = s0y + n * kR2IncY;
+    ux = (double)(Ux >> 11) * 0x1p-53;
+    uy = (double)(Uy >> 11) * 0x1p-53;
+}
+
+// --------------------------------------------------------------- Philox ----
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The 32x32->64 products
+// map onto v_mad_u64_u32; the key schedule is wave-uniform and stays scalar.
+struct U32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U32x4{c0, c1, c2, c3};
+}
+
+// Block t of realisation `real` under key `seed`: counter (t, real lo, real hi, 0).
+__device__ __forceinline__ U32x4 coef_block(uint64_t seed, uint64_t real, uint32_t t) {
+    return philox4x32_10(t, (uint32_t)real, (uint32_t)(real >> 32), 0u, (uint32_t)seed,
+                         (uint32_t)(seed >> 32));
+}
+
+// 32-bit word -> (2m+1) 2^-24 with m = x >> 9: exact in binary32, in (0,1).
+__device__ __forceinline__ float word_uniform_f32(uint32_t x) {
+    return (float)(x >> 9) * 0x1p-23f + 0x1p-24f;
+}
+__device__ __forceinline__ double word_uniform_f64(uint32_t x) {
+    return ((double)(x >> 9) + 0.5) * 0x1p-23;
+}
+
+// sin and cos of 2 pi u for u in (0,1) given exactly in binary32:
+// u - 1/2 is exact and lies in [-1/2, 1/2), where the hardware
+// revolution-domain sine/cosine are accurate to ~1.3e-7 absolute.
+__device__ __forceinline__ void sincos2pi_unit_f32(float u, float& s, float& c) {
+    float v = u - 0.5f;
+    s = -__builtin_amdgcn_sinf(v);
+    c = -__builtin_amdgcn_cosf(v);
+}
+
+// Box-Muller on binary32: (u1, u2) -> rho (cos 2 pi u2, sin 2 pi u2),
+// rho = sqrt(-2 ln u1) = sqrt(-2 ln2 log2 u1).
+__device__ __forceinline__ void box_muller_f32(float u1, float u2, float& g0, float& g1) {
+    float rho = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+    float s, c;
+    sincos2pi_unit_f32(u2, s, c);
+    g0 = rho * c;
+    g1 = rho * s;
+}
+
+// Four consecutive coefficients c[4t .. 4t+3] of one realisation
+// (Gaussian cos/sin mode), binary32.
+__device__ __forceinline__ void gauss4_f32(uint64_t seed, uint64_t real, uint32_t t, float g[4]) {
+    U32x4 x = coef_block(seed, real, t);
+    box_muller_f32(word_uniform_f32(x.x), word_uniform_f32(x.y), g[0], g[1]);
+    box_muller_f32(word_uniform_f32(x.z), word_uniform_f32(x.w), g[2], g[3]);
+}
+
+// Eq. 3 mode for frequency k: (a, b) = sqrt2 R_n (cos 2 pi R_u, -sin 2 pi R_u).
+__device__ __forceinline__ void eq3_pair_f32(uint64_t seed, uint64_t real, uint32_t k, float& a,
+                                             float& b) {
+    U32x4 x = coef_block(seed, real, k);
+    float rn, unused;
+    box_muller_f32(word_uniform_f32(x.x), word_uniform_f32(x.y), rn, unused);
+    float s, c;
+    sincos2pi_unit_f32(word_uniform_f32(x.z), s, c);
+    a = 1.4142135623730951f * rn * c;
+    b = -1.4142135623730951f * rn * s;
+}
+
+// Coefficients c[4t .. 4t+3] in either mode (mode is wave-uniform).
+__device__ __forceinline__ void coef4_f32(uint64_t seed, uint64_t real, uint32_t t, int mode,
+                                          float g[4]) {
+    if (mode == 0) {
+        gauss4_f32(seed, real, t, g);
+    } else {
+        eq3_pair_f32(seed, real, 2u * t, g[0], g[1]);
+        eq3_pair_f32(seed, real, 2u * t + 1u, g[2], g[3]);
+    }
+}
+
+// binary64 versions (FP64 path).
+__device__ __forceinline__ void box_muller_f64(double u1, double u2, double& g0, double& g1) {
+    double rho = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    g0 = rho * c;
+    g1 = rho * s;
+}
+
+__device__ __forceinline__ void coef4_f64(uint64_t seed, uint64_t real, uint32_t t, int mode,
+                                          double g[4]) {
+    if (mode == 0) {
+        U32x4 x = coef_block(seed, real, t);
+        box_muller_f64(word_uniform_f64(x.x), word_uniform_f64(x.y), g[0], g[1]);
+        box_muller_f64(word_uniform_f64(x.z), word_uniform_f64(x.w), g[2], g[3]);
+    } else {
+        for (int h = 0; h < 2; ++h) {
+            U32x4 x = coef_block(seed, real, 2u * t + (uint32_t)h);
+            double rn, unused;
+            box_muller_f64(word_uniform_f64(x.x), word_uniform_f64(x.y), rn, unused);
+            double s, c;
+            sincospi(2.0 * word_uniform_f64(x.z), &s, &c);
+            g[2 * h] = 1.4142135623730951 * rn * c;
+            g[2 * h + 1] = -1.4142135623730951 * rn * s;
+        }
+    }
+}
+
+// ------------------------------------------------------ PSD and filter ----
+__device__ __forceinline__ double psd_phase(int model, double c, double r0_m53, double inv_L02,
+                                            double f) {
+    double q = f * f + (model == 1 ? inv_L02 : 0.0);
+    if (q == 0.0) return 0.0;
+    return c * r0_m53 * pow(q, -11.0 / 6.0);
+}
+
+// Circular aperture filter with central obstruction (Eq. 7), signed.
+__device__ __forceinline__ double aperture_filter(double D, double d, double f) {
+    if (f == 0.0) return 1.0;
+    const double pi = 3.141592653589793;
+    double num = D * j1(pi * D * f);
+    if (d > 0.0) num -= d * j1(pi * d * f);
+    return 2.0 * num / (pi * (D * D - d * d) * f);
+}
+
+// Fractional part of t to [-1/2, 1/2] in binary64 (exact).
+__device__ __forceinline__ double frac_centered(double t) { return t - rint(t); }
+
+}  // namespace qrfs

@@ -1,0 +1,67 @@
+// qrfs_internal.hpp -- launchers shared by the C ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qrfs {
+
+// Exact Kolmogorov constant of the phase PSD in cycles/m,
+// Gamma(11/6)^2 / (2 pi^(11/3)) (24/5 Gamma(6/5))^(5/6) (Eq. 7 prints 0.02289).
+constexpr double kPsdConstant = 0.022895587108555181;
+
+enum Basis : int {
+    BASIS_PHASE = 0,   // (cos, sin)(2 pi f.x_p) w_k
+    BASIS_PISTON = 1,  // (cos, sin)(2 pi f.c_p) w_k F(D_p, d_p, |f_k|)
+    BASIS_DIFF = 2,    // (cos 2 pi f.B_p - 1, sin 2 pi f.B_p) w_k
+};
+
+enum Epilogue : int {
+    EPI_STORE = 0,  // write the sums [R][P]
+    EPI_SFSUM = 1,  // per column: sum of squares and fourth powers over rows
+};
+
+// One launch of the fused coefficient x basis contraction over the sets
+// [set0, set1).  Frequency arrays hold those sets contiguously: set s at
+// offset (s - set0) * K.
+struct SumArgs {
+    int64_t K;
+    const double* fx;
+    const double* fy;
+    const double* w;
+    int64_t P;
+    const double* px;
+    const double* py;
+    const double* apD;  // BASIS_PISTON only
+    const double* apd;
+    int64_t R;
+    int64_t R_block;
+    int64_t set0;
+    int64_t set1;
+    uint64_t seed;
+    uint64_t counter;
+    int32_t mode;
+    const double* coef;  // [R][2K] or nullptr
+    void* out;           // EPI_STORE: float or double [R][P]
+    double* partial;     // EPI_SFSUM: [row tiles of this launch][P][2]
+};
+
+// Row tiles one set occupies in `launch_sum` for this precision and R_block
+// (needed to size the partial-sum buffer).
+int64_t sum_row_tiles_per_set(int precision, int basis, int64_t R_block, int64_t P);
+
+hipError_t launch_sum(int precision, int basis, int epi, const SumArgs& a, hipStream_t st);
+
+hipError_t launch_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n_sets,
+                         int64_t K, int32_t N, double df, double fmin, double fmax, double* fx,
+                         double* fy, double* area, hipStream_t st);
+
+hipError_t launch_weights(int model, double c, double r0, double L0, int has_ap, double D,
+                          double d, int64_t n, const double* fx, const double* fy,
+                          const double* area, double* w, hipStream_t st);
+
+// sf[p] = S2/R, stderr[p] from partial[n_tiles][P][2] in a fixed order.
+hipError_t launch_reduce_sf(const double* partial, int64_t n_tiles, int64_t P, int64_t R,
+                            double* sf, double* sf_stderr, hipStream_t st);
+
+}  // namespace qrfs

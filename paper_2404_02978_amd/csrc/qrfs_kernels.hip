@@ -1,0 +1,631 @@
+// qrfs_kernels.hip -- gfx950 kernels of the quasi-random frequency sampling
+// path (arXiv 2404.02978): R2 sampler, PSD/aperture weights, the fused
+// coefficient x basis contraction of Eq. 3 (FP64 vector ALU, FP32 MFMA and
+// split-BF16 MFMA), and the fixed-order structure-function reduction.
+#include "qrfs_device.hpp"
+#include "qrfs_internal.hpp"
+
+namespace qrfs {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------- sampler ----
+// One thread per frequency.  Point n = index + 1 + i of the R2 sequence
+// (Sec. 3.2, Eq. 6), mapped by Eq. 5 (Cartesian) or the log-polar map.
+__global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n,
+                         int64_t K, double L, double fmin, double lr, double* __restrict__ fx,
+                         double* __restrict__ fy, double* __restrict__ area) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double ux, uy;
+    r2_point(s0x, s0y, index + 1u + (uint64_t)i, ux, uy);
+    if (scheme == 0) {
+        fx[i] = L * (ux - 0.5);
+        fy[i] = L * (uy - 0.5);
+        area[i] = L * L / (double)K;
+    } else {
+        double f = fmin * exp(lr * ux);
+        double s, c;
+        sincospi(2.0 * uy, &s, &c);
+        fx[i] = f * c;
+        fy[i] = f * s;
+        area[i] = 2.0 * 3.141592653589793 * lr * f * f / (double)K;
+    }
+}
+
+// ------------------------------------------------------------- weights ----
+// w = sqrt(W(|f|) area) [x F(|f|)], the amplitude of Eq. 3 (Eq. 7 filter).
+__global__ void k_weights(int model, double c, double r0_m53, double inv_L02, int has_ap,
+                          double D, double d, int64_t n, const double* __restrict__ fx,
+                          const double* __restrict__ fy, const double* __restrict__ area,
+                          double* __restrict__ w) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double f = sqrt(fx[i] * fx[i] + fy[i] * fy[i]);
+    double v = sqrt(psd_phase(model, c, r0_m53, inv_L02, f) * area[i]);
+    if (has_ap) v *= aperture_filter(D, d, f);
+    w[i] = v;
+}
+
+// --------------------------------------------------- tile bookkeeping ----
+struct TileInfo {
+    int64_t sl;         // set index within the launch
+    int64_t rt;         // row tile within the set
+    int64_t ct;         // column tile
+    int64_t row_begin;  // first row of the tile
+    int64_t row_end;    // one past the last valid row of the set
+};
+
+__device__ __forceinline__ TileInfo decode_tile(const SumArgs& a, int64_t row_tiles,
+                                                int64_t col_tiles, int64_t MT) {
+    TileInfo t;
+    int64_t b = blockIdx.x;
+    t.ct = b % col_tiles;
+    b /= col_tiles;
+    t.rt = b % row_tiles;
+    t.sl = b / row_tiles;
+    int64_t s = a.set0 + t.sl;
+    t.row_begin = s * a.R_block + t.rt * MT;
+    int64_t se = (s + 1) * a.R_block;
+    t.row_end = se < a.R ? se : a.R;
+    return t;
+}
+
+// -------------------------------------------------- FP64 vector kernel ----
+// Tile: 32 rows x 32 columns, 256 threads; thread (tp, tg) owns column tp
+// and rows 4 tg .. 4 tg + 3.  Per chunk of 32 frequencies the block builds
+// the FP64 coefficient tile and the FP64 basis tile in LDS, then every
+// thread accumulates its 4 rows in FP64, frequency by frequency.
+constexpr int F64_TP = 32;
+constexpr int F64_TG = 8;
+constexpr int F64_RPT = 4;
+constexpr int F64_TR = F64_TG * F64_RPT;
+constexpr int F64_KC = 32;
+
+template <int BASIS, int EPI>
+__global__ __launch_bounds__(256) void k_sum_f64(SumArgs a, int64_t row_tiles,
+                                                 int64_t col_tiles) {
+    __shared__ double sBc[F64_KC][F64_TP];
+    __shared__ double sBs[F64_KC][F64_TP];
+    __shared__ double sC[F64_TR][2 * F64_KC + 1];
+    __shared__ double sfx[F64_KC], sfy[F64_KC], sw[F64_KC];
+    __shared__ double spx[F64_TP], spy[F64_TP], sD[F64_TP], sd[F64_TP];
+    __shared__ double sred[F64_TG][F64_TP][2];
+
+    const int tid = threadIdx.x;
+    const int tp = tid % F64_TP;
+    const int tg = tid / F64_TP;
+    const TileInfo ti = decode_tile(a, row_tiles, col_tiles, F64_TR);
+    const int64_t col0 = ti.ct * F64_TP;
+    if (tid < F64_TP) {
+        int64_t p = col0 + tid;
+        bool ok = p < a.P;
+        spx[tid] = ok ? a.px[p] : 0.0;
+        spy[tid] = ok ? a.py[p] : 0.0;
+        if (BASIS == BASIS_PISTON) {
+            sD[tid] = ok ? a.apD[p] : 1.0;
+            sd[tid] = ok ? a.apd[p] : 0.0;
+        }
+    }
+    const double* fx = a.fx + ti.sl * a.K;
+    const double* fy = a.fy + ti.sl * a.K;
+    const double* w = a.w + ti.sl * a.K;
+    const int64_t twoK = 2 * a.K;
+
+    double acc[F64_RPT];
+#pragma unroll
+    for (int q = 0; q < F64_RPT; ++q) acc[q] = 0.0;
+
+    for (int64_t k0 = 0; k0 < a.K; k0 += F64_KC) {
+        __syncthreads();
+        if (tid < F64_KC) {
+            int64_t k = k0 + tid;
+            bool ok = k < a.K;
+            sfx[tid] = ok ? fx[k] : 0.0;
+            sfy[tid] = ok ? fy[k] : 0.0;
+            sw[tid] = ok ? w[k] : 0.0;
+        }
+        // coefficients: 32 rows x 16 Philox blocks (4 coefficients each)
+        for (int i = tid; i < F64_TR * (F64_KC / 2); i += 256) {
+            int rr = i / (F64_KC / 2);
+            int bt = i % (F64_KC / 2);
+            int64_t r = ti.row_begin + rr;
+            double g[4] = {0.0, 0.0, 0.0, 0.0};
+            if (r < ti.row_end) {
+                if (a.coef) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        int64_t j = 2 * k0 + 4 * bt + q;
+                        g[q] = j < twoK ? a.coef[r * twoK + j] : 0.0;
+                    }
+                } else {
+                    coef4_f64(a.seed, a.counter + (uint64_t)r, (uint32_t)(k0 / 2 + bt), a.mode, g);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sC[rr][4 * bt + q] = g[q];
+        }
+        __syncthreads();
+        for (int i = tid; i < F64_KC * F64_TP; i += 256) {
+            int kk = i / F64_TP;
+            int pp = i % F64_TP;
+            double t = sfx[kk] * spx[pp] + sfy[kk] * spy[pp];
+            double rf = frac_centered(t);
+            double s, c;
+            if (BASIS == BASIS_DIFF) {
+                double sh = sinpi(rf);
+                c = -2.0 * sh * sh;
+                s = sinpi(2.0 * rf);
+            } else {
+                sincospi(2.0 * rf, &s, &c);
+            }
+            double amp = sw[kk];
+            if (BASIS == BASIS_PISTON)
+                amp *= aperture_filter(sD[pp], sd[pp], sqrt(sfx[kk] * sfx[kk] + sfy[kk] * sfy[kk]));
+            sBc[kk][pp] = amp * c;
+            sBs[kk][pp] = amp * s;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < F64_KC; ++kk) {
+            double cb = sBc[kk][tp];
+            double sb = sBs[kk][tp];
+#pragma unroll
+            for (int q = 0; q < F64_RPT; ++q) {
+                const double* cr = sC[tg * F64_RPT + q];
+                acc[q] = fma(cr[2 * kk], cb, fma(cr[2 * kk + 1], sb, acc[q]));
+            }
+        }
+    }
+
+    const int64_t col = col0 + tp;
+    if (EPI == EPI_STORE) {
+        double* out = (double*)a.out;
+#pragma unroll
+        for (int q = 0; q < F64_RPT; ++q) {
+            int64_t r = ti.row_begin + tg * F64_RPT + q;
+            if (r < ti.row_end && col < a.P) out[r * a.P + col] = acc[q];
+        }
+    } else {
+        double s2 = 0.0, s4 = 0.0;
+#pragma unroll
+        for (int q = 0; q < F64_RPT; ++q) {
+            int64_t r = ti.row_begin + tg * F64_RPT + q;
+            if (r < ti.row_end) {
+                double d2 = acc[q] * acc[q];
+                s2 += d2;
+                s4 += d2 * d2;
+            }
+        }
+        sred[tg][tp][0] = s2;
+        sred[tg][tp][1] = s4;
+        __syncthreads();
+        if (tid < F64_TP && col < a.P) {
+            double t2 = 0.0, t4 = 0.0;
+            for (int g = 0; g < F64_TG; ++g) {
+                t2 += sred[g][tid][0];
+                t4 += sred[g][tid][1];
+            }
+            double* dst = a.partial + ((ti.sl * row_tiles + ti.rt) * a.P + col) * 2;
+            dst[0] = t2;
+            dst[1] = t4;
+        }
+    }
+}
+
+// --------------------------------------------------------- MFMA kernel ----
+// One block = WV waves (WV = blockDim.x / 64 in 1..4).  Wave v owns rows
+// [32 MW v, 32 MW (v+1)) of the tile and all NT = 32 NB columns, so each
+// lane draws exactly the coefficients its own MFMA A-operand needs (no LDS
+// traffic for coefficients) while the basis tile is shared through LDS.
+//
+// Per chunk of KC = 16 frequencies:
+//   - the block evaluates the basis: t = f.x in FP64, r = t - rint(t),
+//     hardware sin/cos of 2 pi r in FP32, times the weight (and the
+//     aperture filter for pistons); stored as [column][2 KC] floats (FP32)
+//     or as bf16 hi and lo planes (split-BF16);
+//   - FP32: 16 steps of v_mfma_f32_32x32x2_f32.  Lane (r, h) holds the 4
+//     coefficients of Philox block t = k0/2 + 2m + h, so step (m, q) uses
+//     chunk-local contraction index j = 8m + 4h + q on both operands (the
+//     contraction order is permuted, the result is not);
+//   - split-BF16: 2 steps of v_mfma_f32_32x32x16_bf16 x 3 (hi.hi, hi.lo,
+//     lo.hi).  Lane (r, h) holds coefficients j = 16 s + 8 h + 0..7, the
+//     natural order.
+// The MFMA accumulators are added to a second FP32 accumulator every FLUSH
+// chunks (64 frequencies), which keeps the rounding error of long sums at
+// ~u (sqrt(64) + sqrt(K/64)) instead of ~u sqrt(K).
+constexpr int KC = 16;
+constexpr int FLUSH = 4;
+constexpr int STR_F32 = 2 * KC + 4;   // floats per basis column (16-byte rows, skewed banks)
+constexpr int STR_BF16 = 2 * KC + 8;  // bf16 per basis column
+
+template <int PREC, int BASIS>
+__device__ __forceinline__ void basis_pair(double t, double amp, float& cb, float& sb) {
+    float r = (float)frac_centered(t);
+    if (BASIS == BASIS_DIFF) {
+        float sh = __builtin_amdgcn_sinf(0.5f * r);  // sin(pi r)
+        cb = -2.0f * sh * sh;                         // cos(2 pi r) - 1
+        sb = __builtin_amdgcn_sinf(r);
+    } else {
+        cb = __builtin_amdgcn_cosf(r);
+        sb = __builtin_amdgcn_sinf(r);
+    }
+    float fa = (float)amp;
+    cb *= fa;
+    sb *= fa;
+}
+
+template <int PREC, int BASIS, int EPI, int MW, int NB>
+__global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
+                                                  int64_t col_tiles) {
+    constexpr int NT = 32 * NB;
+    constexpr int NBF = PREC == 1 ? NT * STR_F32 : 4;
+    constexpr int NBH = PREC == 2 ? NT * STR_BF16 : 8;
+    __shared__ __attribute__((aligned(16))) float sBf[NBF];
+    __shared__ __attribute__((aligned(16))) __bf16 sBh[NBH];
+    __shared__ __attribute__((aligned(16))) __bf16 sBl[NBH];
+    __shared__ double sfx[KC], sfy[KC], sw[KC];
+    __shared__ double spx[NT], spy[NT], sD[NT], sd[NT];
+    __shared__ double sred[4][NT][2];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int WV = blockDim.x >> 6;
+    const int lr = lane & 31;
+    const int lh = lane >> 5;
+    const int64_t MT = 32 * MW * WV;
+    const TileInfo ti = decode_tile(a, row_tiles, col_tiles, MT);
+    const int64_t col0 = ti.ct * NT;
+
+    for (int i = threadIdx.x; i < NT; i += blockDim.x) {
+        int64_t p = col0 + i;
+        bool ok = p < a.P;
+        spx[i] = ok ? a.px[p] : 0.0;
+        spy[i] = ok ? a.py[p] : 0.0;
+        if (BASIS == BASIS_PISTON) {
+            sD[i] = ok ? a.apD[p] : 1.0;
+            sd[i] = ok ? a.apd[p] : 0.0;
+        }
+    }
+
+    int64_t myrow[MW];
+    bool rowok[MW];
+#pragma unroll
+    for (int mw = 0; mw < MW; ++mw) {
+        myrow[mw] = ti.row_begin + (int64_t)(wave * MW + mw) * 32 + lr;
+        rowok[mw] = myrow[mw] < ti.row_end;
+    }
+    const double* fx = a.fx + ti.sl * a.K;
+    const double* fy = a.fy + ti.sl * a.K;
+    const double* w = a.w + ti.sl * a.K;
+    const int64_t twoK = 2 * a.K;
+
+    f32x16 acc[MW][NB];
+    f32x16 mst[MW][NB];
+#pragma unroll
+    for (int mw = 0; mw < MW; ++mw)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                acc[mw][nb][i] = 0.0f;
+                mst[mw][nb][i] = 0.0f;
+            }
+        }
+
+    const int64_t nchunks = (a.K + KC - 1) / KC;
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+        const int64_t k0 = ch * KC;
+        __syncthreads();
+        if (threadIdx.x < KC) {
+            int64_t k = k0 + threadIdx.x;
+            bool ok = k < a.K;
+            sfx[threadIdx.x] = ok ? fx[k] : 0.0;
+            sfy[threadIdx.x] = ok ? fy[k] : 0.0;
+            sw[threadIdx.x] = ok ? w[k] : 0.0;
+        }
+        __syncthreads();
+        // basis tile: frequency index fastest so neighbouring threads write
+        // neighbouring LDS words
+        for (int i = threadIdx.x; i < KC * NT; i += blockDim.x) {
+            const int kk = i % KC;
+            const int pp = i / KC;
+            double t = sfx[kk] * spx[pp] + sfy[kk] * spy[pp];
+            double amp = sw[kk];
+            if (BASIS == BASIS_PISTON)
+                amp *= aperture_filter(sD[pp], sd[pp], sqrt(sfx[kk] * sfx[kk] + sfy[kk] * sfy[kk]));
+            float cb, sb;
+            basis_pair<PREC, BASIS>(t, amp, cb, sb);
+            if (PREC == 1) {
+                sBf[pp * STR_F32 + 2 * kk] = cb;
+                sBf[pp * STR_F32 + 2 * kk + 1] = sb;
+            } else {
+                __bf16 ch_ = (__bf16)cb;
+                __bf16 sh_ = (__bf16)sb;
+                sBh[pp * STR_BF16 + 2 * kk] = ch_;
+                sBh[pp * STR_BF16 + 2 * kk + 1] = sh_;
+                sBl[pp * STR_BF16 + 2 * kk] = (__bf16)(cb - (float)ch_);
+                sBl[pp * STR_BF16 + 2 * kk + 1] = (__bf16)(sb - (float)sh_);
+            }
+        }
+        __syncthreads();
+
+        if (PREC == 1) {
+#pragma unroll
+            for (int m = 0; m < KC / 4; ++m) {
+                const uint32_t t = (uint32_t)(k0 / 2) + 2u * m + (uint32_t)lh;
+                float av[MW][4];
+#pragma unroll
+                for (int mw = 0; mw < MW; ++mw) {
+                    if (a.coef) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            int64_t j = 4 * (int64_t)t + q;
+                            av[mw][q] = (rowok[mw] && j < twoK) ? (float)a.coef[myrow[mw] * twoK + j]
+                                                                : 0.0f;
+                        }
+                    } else {
+                        coef4_f32(a.seed, a.counter + (uint64_t)myrow[mw], t, a.mode, av[mw]);
+                        if (!rowok[mw]) av[mw][0] = av[mw][1] = av[mw][2] = av[mw][3] = 0.0f;
+                    }
+                }
+                f32x4 bv[NB];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    bv[nb] = *(const f32x4*)&sBf[(nb * 32 + lr) * STR_F32 + 8 * m + 4 * lh];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int mw = 0; mw < MW; ++mw)
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb)
+                            acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                                av[mw][q], bv[nb][q], acc[mw][nb], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int sg = 0; sg < KC / 8; ++sg) {
+                const uint32_t t = (uint32_t)(k0 / 2) + 4u * sg + 2u * (uint32_t)lh;
+                bf16x8 ah[MW], al[MW];
+#pragma unroll
+                for (int mw = 0; mw < MW; ++mw) {
+                    float g[8];
+                    if (a.coef) {
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            int64_t j = 4 * (int64_t)t + q;
+                            g[q] = (rowok[mw] && j < twoK) ? (float)a.coef[myrow[mw] * twoK + j] : 0.0f;
+                        }
+                    } else {
+                        coef4_f32(a.seed, a.counter + (uint64_t)myrow[mw], t, a.mode, g);
+                        coef4_f32(a.seed, a.counter + (uint64_t)myrow[mw], t + 1u, a.mode, g + 4);
+                        if (!rowok[mw])
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) g[q] = 0.0f;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        __bf16 hi = (__bf16)g[q];
+                        ah[mw][q] = hi;
+                        al[mw][q] = (__bf16)(g[q] - (float)hi);
+                    }
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int off = (nb * 32 + lr) * STR_BF16 + 16 * sg + 8 * lh;
+                    bf16x8 bh = *(const bf16x8*)&sBh[off];
+                    bf16x8 bl = *(const bf16x8*)&sBl[off];
+#pragma unroll
+                    for (int mw = 0; mw < MW; ++mw) {
+                        acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mw], bh, acc[mw][nb], 0, 0, 0);
+                        acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mw], bl, acc[mw][nb], 0, 0, 0);
+                        acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[mw], bh, acc[mw][nb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+
+        if ((ch % FLUSH) == FLUSH - 1 || ch == nchunks - 1) {
+#pragma unroll
+            for (int mw = 0; mw < MW; ++mw)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    mst[mw][nb] += acc[mw][nb];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) acc[mw][nb][i] = 0.0f;
+                }
+        }
+    }
+
+    if (EPI == EPI_STORE) {
+        float* out = (float*)a.out;
+#pragma unroll
+        for (int mw = 0; mw < MW; ++mw)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int64_t col = col0 + nb * 32 + lr;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    int64_t r = ti.row_begin + (int64_t)(wave * MW + mw) * 32 + 8 * (i / 4) + 4 * lh + (i % 4);
+                    if (r < ti.row_end && col < a.P) out[r * a.P + col] = mst[mw][nb][i];
+                }
+            }
+    } else {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            double s2 = 0.0, s4 = 0.0;
+#pragma unroll
+            for (int mw = 0; mw < MW; ++mw)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    int64_t r = ti.row_begin + (int64_t)(wave * MW + mw) * 32 + 8 * (i / 4) + 4 * lh + (i % 4);
+                    if (r < ti.row_end) {
+                        double d = (double)mst[mw][nb][i];
+                        double d2 = d * d;
+                        s2 += d2;
+                        s4 += d2 * d2;
+                    }
+                }
+            s2 += __shfl_xor(s2, 32);
+            s4 += __shfl_xor(s4, 32);
+            if (lh == 0) {
+                sred[wave][nb * 32 + lr][0] = s2;
+                sred[wave][nb * 32 + lr][1] = s4;
+            }
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < NT; c += blockDim.x) {
+            const int64_t col = col0 + c;
+            if (col < a.P) {
+                double t2 = 0.0, t4 = 0.0;
+                for (int v = 0; v < WV; ++v) {
+                    t2 += sred[v][c][0];
+                    t4 += sred[v][c][1];
+                }
+                double* dst = a.partial + ((ti.sl * row_tiles + ti.rt) * a.P + col) * 2;
+                dst[0] = t2;
+                dst[1] = t4;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------- reduce ----
+// One block per column; partial sums over row tiles in a fixed order
+// (strided by thread, then a fixed tree), so results are bit-reproducible.
+__global__ __launch_bounds__(256) void k_reduce_sf(const double* __restrict__ partial,
+                                                   int64_t n_tiles, int64_t P, int64_t R,
+                                                   double* __restrict__ sf,
+                                                   double* __restrict__ sf_stderr) {
+    __shared__ double r2[256], r4[256];
+    const int64_t p = blockIdx.x;
+    double s2 = 0.0, s4 = 0.0;
+    for (int64_t t = threadIdx.x; t < n_tiles; t += 256) {
+        s2 += partial[(t * P + p) * 2];
+        s4 += partial[(t * P + p) * 2 + 1];
+    }
+    r2[threadIdx.x] = s2;
+    r4[threadIdx.x] = s4;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            r2[threadIdx.x] += r2[threadIdx.x + h];
+            r4[threadIdx.x] += r4[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double S2 = r2[0], S4 = r4[0];
+        double n = (double)R;
+        sf[p] = S2 / n;
+        if (sf_stderr) {
+            double var = R > 1 ? (S4 - S2 * S2 / n) / (n - 1.0) : 0.0;
+            sf_stderr[p] = sqrt(var > 0.0 ? var / n : 0.0);
+        }
+    }
+}
+
+// ----------------------------------------------------------- launchers ----
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+hipError_t launch_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n_sets,
+                         int64_t K, int32_t N, double df, double fmin, double fmax, double* fx,
+                         double* fy, double* area, hipStream_t st) {
+    int64_t n = n_sets * K;
+    double L = (double)N * df;
+    double lr = scheme == 1 ? log(fmax / fmin) : 0.0;
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, scheme, s0x, s0y,
+                       index, n, K, L, fmin, lr, fx, fy, area);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights(int model, double c, double r0, double L0, int has_ap, double D,
+                          double d, int64_t n, const double* fx, const double* fy,
+                          const double* area, double* w, hipStream_t st) {
+    double r0_m53 = pow(r0, -5.0 / 3.0);
+    double inv_L02 = model == 1 ? 1.0 / (L0 * L0) : 0.0;
+    hipLaunchKernelGGL(k_weights, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, model, c, r0_m53,
+                       inv_L02, has_ap, D, d, n, fx, fy, area, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_sf(const double* partial, int64_t n_tiles, int64_t P, int64_t R,
+                            double* sf, double* sf_stderr, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_sf, dim3((unsigned)P), dim3(256), 0, st, partial, n_tiles, P, R, sf,
+                       sf_stderr);
+    return hipGetLastError();
+}
+
+// launch shapes of the MFMA kernel
+struct MfmaShape {
+    int MW, NB, WV;
+};
+
+static MfmaShape mfma_shape(int basis, int64_t R_block, int64_t P) {
+    MfmaShape s;
+    if (basis == BASIS_PHASE && P > 32) {
+        s.MW = 2;
+        s.NB = 2;
+    } else {
+        s.MW = 1;
+        s.NB = 1;
+    }
+    int64_t wv = cdiv(R_block, 32 * s.MW);
+    s.WV = (int)(wv > 4 ? 4 : wv);
+    return s;
+}
+
+int64_t sum_row_tiles_per_set(int precision, int basis, int64_t R_block, int64_t P) {
+    if (precision == 0) return cdiv(R_block, F64_TR);
+    MfmaShape s = mfma_shape(basis, R_block, P);
+    return cdiv(R_block, 32 * s.MW * s.WV);
+}
+
+template <int BASIS, int EPI>
+static hipError_t launch_f64(const SumArgs& a, hipStream_t st) {
+    int64_t row_tiles = cdiv(a.R_block, F64_TR);
+    int64_t col_tiles = cdiv(a.P, F64_TP);
+    int64_t blocks = (a.set1 - a.set0) * row_tiles * col_tiles;
+    hipLaunchKernelGGL((k_sum_f64<BASIS, EPI>), dim3((unsigned)blocks), dim3(256), 0, st, a,
+                       row_tiles, col_tiles);
+    return hipGetLastError();
+}
+
+template <int PREC, int BASIS, int EPI, int MW, int NB>
+static hipError_t launch_mfma_t(const SumArgs& a, int WV, hipStream_t st) {
+    int64_t MT = 32 * MW * WV;
+    int64_t row_tiles = cdiv(a.R_block, MT);
+    int64_t col_tiles = cdiv(a.P, 32 * NB);
+    int64_t blocks = (a.set1 - a.set0) * row_tiles * col_tiles;
+    hipLaunchKernelGGL((k_sum_mfma<PREC, BASIS, EPI, MW, NB>), dim3((unsigned)blocks),
+                       dim3(64 * WV), 0, st, a, row_tiles, col_tiles);
+    return hipGetLastError();
+}
+
+template <int PREC, int BASIS, int EPI>
+static hipError_t launch_mfma(const SumArgs& a, hipStream_t st) {
+    MfmaShape s = mfma_shape(BASIS, a.R_block, a.P);
+    if (s.MW == 2) return launch_mfma_t<PREC, BASIS, EPI, 2, 2>(a, s.WV, st);
+    return launch_mfma_t<PREC, BASIS, EPI, 1, 1>(a, s.WV, st);
+}
+
+template <int BASIS, int EPI>
+static hipError_t launch_be(int precision, const SumArgs& a, hipStream_t st) {
+    if (precision == 0) return launch_f64<BASIS, EPI>(a, st);
+    if (precision == 1) return launch_mfma<1, BASIS, EPI>(a, st);
+    return launch_mfma<2, BASIS, EPI>(a, st);
+}
+
+hipError_t launch_sum(int precision, int basis, int epi, const SumArgs& a, hipStream_t st) {
+    if (a.set1 <= a.set0) return hipSuccess;
+    if (epi == EPI_STORE) {
+        if (basis == BASIS_PHASE) return launch_be<BASIS_PHASE, EPI_STORE>(precision, a, st);
+        if (basis == BASIS_PISTON) return launch_be<BASIS_PISTON, EPI_STORE>(precision, a, st);
+        return launch_be<BASIS_DIFF, EPI_STORE>(precision, a, st);
+    }
+    return launch_be<BASIS_DIFF, EPI_SFSUM>(precision, a, st);
+}
+
+}  // namespace qrfs

@@ -1,0 +1,108 @@
+"""Host-side checks of libqrfs (no GPU needed): the library loads, exports
+every entry point include/qrfs.h declares, and rejects bad arguments with
+the documented status codes before touching any device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qrfs.h")
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2404_02978_amd as q
+    if not os.path.exists(q.LIB_PATH):
+        from paper_2404_02978_amd import build
+        build.build()
+    q.load_library()
+    return q
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"QRFS_API\s+[\w\s\*]+?\b(qrfs_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(q):
+    lib = q.load_library()
+    names = declared_symbols()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_abi_version_and_strings(q):
+    lib = q.load_library()
+    assert lib.qrfs_abi_version() == 1
+    assert lib.qrfs_error_string(0) == b"success"
+    assert lib.qrfs_error_string(-1) == b"invalid argument"
+    assert lib.qrfs_error_string(-4) == b"unsupported"
+
+
+def _null():
+    return ctypes.c_void_p(8)  # aligned non-null placeholder, never dereferenced
+
+
+def test_argument_checks_precede_device_use(q):
+    lib = q.load_library()
+    p = _null()
+    rng = q.Rng(0, 0, 0)
+    # R_block > R
+    st = lib.qrfs_synthesize_phase(None, 10, p, p, p, 4, p, p, 5, 6, ctypes.byref(rng), None, 1,
+                                   p, None)
+    assert st == q.ERR_INVALID_ARG
+    assert b"R_block" in lib.qrfs_last_error_detail()
+    # unknown precision
+    st = lib.qrfs_synthesize_phase(None, 10, p, p, p, 4, p, p, 5, 5, ctypes.byref(rng), None, 7,
+                                   p, None)
+    assert st == q.ERR_INVALID_ARG
+    # K = 0
+    st = lib.qrfs_diff_piston(None, 0, p, p, p, 4, p, p, 5, 5, ctypes.byref(rng), None, 1, p, None)
+    assert st == q.ERR_INVALID_ARG
+    # misaligned array
+    st = lib.qrfs_piston(None, 3, ctypes.c_void_p(12), p, p, 2, p, p, p, p, 5, 5,
+                         ctypes.byref(rng), None, 1, p, None)
+    assert st == q.ERR_INVALID_ARG and b"aligned" in lib.qrfs_last_error_detail()
+    # bad PSD / aperture
+    psd = q.psd(0.1, -3.0)
+    st = lib.qrfs_weights(None, ctypes.byref(psd), None, 3, p, p, p, p, None)
+    assert st == q.ERR_INVALID_ARG and b"L0" in lib.qrfs_last_error_detail()
+    ap = q.Aperture(1.0, 1.5)
+    st = lib.qrfs_weights(None, ctypes.byref(q.psd(0.1, 25.0)), ctypes.byref(ap), 3, p, p, p, p,
+                          None)
+    assert st == q.ERR_INVALID_ARG
+    # sampler checks
+    s = q.logpolar_sampler(2.0, 1.0)
+    st = lib.qrfs_sample_frequencies(None, ctypes.byref(s), 1, 8, p, p, p, None)
+    assert st == q.ERR_INVALID_ARG
+    s = q.cartesian_sampler(0, 0.1)
+    st = lib.qrfs_sample_frequencies(None, ctypes.byref(s), 1, 8, p, p, p, None)
+    assert st == q.ERR_INVALID_ARG
+    s = q.logpolar_sampler(1e-3, 1e2)
+    s.scheme = q.SAMPLER_LEARNED
+    st = lib.qrfs_sample_frequencies(None, ctypes.byref(s), 1, 8, p, p, p, None)
+    assert st == q.ERR_UNSUPPORTED
+    assert s.index == 0  # untouched on error
+    # coefficients without rng
+    st = lib.qrfs_synthesize_phase(None, 10, p, p, p, 4, p, p, 5, 5, None, None, 1, p, None)
+    assert st == q.ERR_INVALID_ARG
+    # structure function without aperture
+    st = lib.qrfs_diff_piston_structure(None, ctypes.byref(q.psd(0.1, 25.0)), None, 4, p, p,
+                                        ctypes.byref(q.logpolar_sampler(1e-3, 1e2)), 8, 10, 10,
+                                        ctypes.byref(rng), 1, p, None, None)
+    assert st == q.ERR_INVALID_ARG
+    # valid arguments, NULL context
+    st = lib.qrfs_synthesize_phase(None, 10, p, p, p, 4, p, p, 5, 5, ctypes.byref(rng), None, 1,
+                                   p, None)
+    assert st == q.ERR_INVALID_ARG and b"context" in lib.qrfs_last_error_detail()
+
+
+def test_no_cpu_fallback_without_gpu(q):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        q.Context(0)

@@ -1,0 +1,325 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (normwise over the compared block, error relative to the RMS of
+the oracle; per-element relative error is meaningless at zero crossings):
+  FP64        1e-11
+  FP32        1e-5   (max error) -- FP32 MFMA, FP32 transcendentals
+  SPLIT_BF16  1e-3   (max error) -- bf16 hi+lo operands, FP32 accumulation
+Integer work (R2 sequence) is compared bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-11, 1: 1e-5, 2: 1e-3}
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2404_02978_amd as q
+    q.load_library()
+    return q
+
+
+@pytest.fixture(scope="module")
+def ctx(q):
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def errs(got, ref):
+    d = got - ref
+    rms = math.sqrt(np.mean(ref * ref))
+    return math.sqrt(np.mean(d * d)) / rms, np.max(np.abs(d)) / rms
+
+
+def report(name, got, ref, tol):
+    e_rms, e_max = errs(got, ref)
+    print(f"{name}: eps_rms={e_rms:.3e} eps_max={e_max:.3e} tol={tol:g}", flush=True)
+    assert e_max <= tol, (name, e_rms, e_max)
+
+
+# ------------------------------------------------------------- sampler ----
+
+@pytest.mark.parametrize("index", [0, 12345, (1 << 40) + 7])
+def test_sampler_cartesian_bit_exact(q, ctx, index):
+    n_sets, K, N, df = 3, 1000, 44, 0.25 / 22
+    s = q.cartesian_sampler(N, df, index=index)
+    fx, fy, area = ctx.sample_frequencies(s, n_sets, K)
+    assert s.index == index + n_sets * K
+    rx, ry, ra = oracle.sample_cartesian(n_sets, K, N, df, index=index)
+    assert np.array_equal(host(fx), rx) and np.array_equal(host(fy), ry)
+    assert np.array_equal(host(area), ra)
+
+
+def test_sampler_logpolar(q, ctx):
+    n_sets, K = 2, 777
+    s = q.logpolar_sampler(1e-3, 1e2, index=99, seed_x=3 << 60, seed_y=5 << 59)
+    fx, fy, area = ctx.sample_frequencies(s, n_sets, K)
+    rx, ry, ra = oracle.sample_logpolar(n_sets, K, 1e-3, 1e2, index=99, s0x=3 << 60, s0y=5 << 59)
+    f = np.hypot(rx, ry)
+    assert np.max(np.abs(host(fx) - rx) / f) < 1e-14
+    assert np.max(np.abs(host(fy) - ry) / f) < 1e-14
+    assert np.max(np.abs(host(area) / ra - 1)) < 1e-14
+
+
+def test_sampler_continuation(q, ctx):
+    """Two calls continue one sequence (Sec. 3.2: never reinitialised)."""
+    s = q.logpolar_sampler(1e-3, 1e2)
+    a = ctx.sample_frequencies(s, 1, 500)[0]
+    b = ctx.sample_frequencies(s, 1, 300)[0]
+    t = q.logpolar_sampler(1e-3, 1e2)
+    c = ctx.sample_frequencies(t, 1, 800)[0]
+    assert torch.equal(torch.cat([a, b]), c)
+
+
+# ------------------------------------------------------------- weights ----
+
+@pytest.mark.parametrize("model,L0,ap", [(1, 25.0, None), (1, 10.0, (1.8, 0.0)),
+                                         (0, None, (8.0, 1.1))])
+def test_weights(q, ctx, model, L0, ap):
+    n_sets, K = 2, 1500
+    s = q.logpolar_sampler(1e-3, 1e2)
+    fx, fy, area = ctx.sample_frequencies(s, n_sets, K)
+    p = q.psd(0.1, L0, model=model)
+    w = ctx.weights(p, fx, fy, area, None if ap is None else q.Aperture(*ap))
+    ref = oracle.weights(host(fx), host(fy), host(area), model=model, r0=0.1,
+                         L0=L0 or 0.0, D=None if ap is None else ap[0],
+                         d=0.0 if ap is None else ap[1])
+    g = host(w)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(g - ref)) / scale < 1e-13
+    assert np.max(np.abs(g - ref) / np.maximum(np.abs(ref), 1e-300 + scale * 1e-12)) < 1e-11
+
+
+def test_weights_kolmogorov_zero_frequency(q, ctx):
+    fx = dev([0.0, 0.5])
+    w = ctx.weights(q.psd(0.1), fx, dev([0.0, 0.0]), dev([1.0, 1.0]))
+    g = host(w)
+    assert g[0] == 0.0 and g[1] > 0.0
+
+
+# ----------------------------------------------------------- synthesis ----
+
+def _freqs(ctx, q, n_sets, K, L0=25.0, ap=None, fmin=1e-3, fmax=1e2, index=0):
+    s = q.logpolar_sampler(fmin, fmax, index=index)
+    fx, fy, area = ctx.sample_frequencies(s, n_sets, K)
+    w = ctx.weights(q.psd(0.1, L0), fx, fy, area, None if ap is None else q.Aperture(*ap))
+    return fx, fy, w
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("R,R_block", [(300, 300), (300, 97), (40, 1), (133, 64)])
+def test_synthesize_parity(q, ctx, precision, R, R_block):
+    K, P = 301, 150
+    n_sets = math.ceil(R / R_block)
+    fx, fy, w = _freqs(ctx, q, n_sets, K)
+    rng = np.random.default_rng(R + R_block)
+    px, py = rng.uniform(-1.5, 1.5, P), rng.uniform(-1.5, 1.5, P)
+    out = ctx.synthesize_phase(K, fx, fy, w, dev(px), dev(py), R, R_block,
+                               rng=q.Rng(11, 1000, 0), precision=precision)
+    ref = oracle.synthesize(host(fx), host(fy), host(w), px, py, R, R_block, K=K, seed=11,
+                            counter=1000)
+    report(f"synth p{precision} R{R} Rb{R_block}", host(out), ref, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_synthesize_phase_workload(q, ctx, precision):
+    """The 32x32-point, K = 1024, R = 128 phase workload, whole output."""
+    cfg = workloads.phase_fp64()
+    K, R = cfg["K"], cfg["R"]
+    for R_block in (R, 1):
+        n_sets = math.ceil(R / R_block)
+        fx, fy, w = _freqs(ctx, q, n_sets, K, L0=cfg["L0"])
+        out = ctx.synthesize_phase(K, fx, fy, w, dev(cfg["px"]), dev(cfg["py"]), R, R_block,
+                                   rng=q.Rng(cfg["seed"], 0, 0), precision=precision)
+        ref = oracle.synthesize(host(fx), host(fy), host(w), cfg["px"], cfg["py"], R, R_block,
+                                K=K, seed=cfg["seed"])
+        report(f"phase workload p{precision} Rb{R_block}", host(out), ref, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_synthesize_given_coefficients(q, ctx, precision):
+    K, P, R, R_block = 70, 45, 90, 33
+    n_sets = math.ceil(R / R_block)
+    fx, fy, w = _freqs(ctx, q, n_sets, K)
+    rng = np.random.default_rng(4)
+    coef = rng.normal(size=(R, 2 * K))
+    px, py = rng.uniform(-1, 1, P), rng.uniform(-1, 1, P)
+    out = ctx.synthesize_phase(K, fx, fy, w, dev(px), dev(py), R, R_block, coef=dev(coef),
+                               precision=precision)
+    ref = oracle.synthesize(host(fx), host(fy), host(w), px, py, R, R_block, K=K, coef=coef)
+    report(f"given coef p{precision}", host(out), ref, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_synthesize_eq3_mode(q, ctx, precision):
+    K, P, R = 123, 37, 70
+    fx, fy, w = _freqs(ctx, q, 1, K)
+    rng = np.random.default_rng(8)
+    px, py = rng.uniform(-1, 1, P), rng.uniform(-1, 1, P)
+    out = ctx.synthesize_phase(K, fx, fy, w, dev(px), dev(py), R, R,
+                               rng=q.Rng(5, 3, q.COEF_EQ3), precision=precision)
+    ref = oracle.synthesize(host(fx), host(fy), host(w), px, py, R, R, K=K, seed=5, counter=3,
+                            mode=1)
+    report(f"eq3 p{precision}", host(out), ref, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_synthesize_degenerate_sizes(q, ctx, precision):
+    for K, P, R in ((1, 1, 1), (1, 33, 2), (17, 1, 65)):
+        fx, fy, w = _freqs(ctx, q, R, K)
+        px, py = np.array([0.3] * P), np.linspace(-1, 1, P)
+        out = ctx.synthesize_phase(K, fx, fy, w, dev(px), dev(py), R, 1,
+                                   rng=q.Rng(1, 0, 0), precision=precision)
+        ref = oracle.synthesize(host(fx), host(fy), host(w), px, py, R, 1, K=K, seed=1)
+        report(f"degenerate K{K} P{P} R{R} p{precision}", host(out), ref, TOL[precision])
+
+
+# -------------------------------------------------------------- piston ----
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_piston_parity(q, ctx, precision):
+    K, R, R_block = 257, 200, 64
+    n_sets = math.ceil(R / R_block)
+    fx, fy, w = _freqs(ctx, q, n_sets, K)
+    cx = np.array([0.0, 56.5, 10.0, -3.0, 120.0])
+    cy = np.array([0.0, 0.0, 20.0, 4.0, -7.0])
+    D = np.array([8.0, 8.0, 1.8, 1.8, 0.5])
+    d = np.array([1.1, 1.1, 0.0, 0.3, 0.0])
+    out = ctx.piston(K, fx, fy, w, dev(cx), dev(cy), dev(D), dev(d), R, R_block,
+                     rng=q.Rng(2, 77, 0), precision=precision)
+    ref = oracle.piston(host(fx), host(fy), host(w), cx, cy, D, d, R, R_block, K=K, seed=2,
+                        counter=77)
+    report(f"piston p{precision}", host(out), ref, TOL[precision])
+
+
+# -------------------------------------------------- differential piston ----
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_diff_piston_parity(q, ctx, precision):
+    cfg = workloads.diffpiston()
+    K, R, R_block = 333, 150, 70
+    n_sets = math.ceil(R / R_block)
+    fx, fy, w = _freqs(ctx, q, n_sets, K, ap=(cfg["D"], 0.0))
+    out = ctx.diff_piston(K, fx, fy, w, dev(cfg["bx"]), dev(cfg["by"]), R, R_block,
+                          rng=q.Rng(0, 5, 0), precision=precision)
+    px = np.concatenate([[0.0], cfg["bx"]])
+    py = np.concatenate([[0.0], cfg["by"]])
+    pist = oracle.synthesize(host(fx), host(fy), host(w), px, py, R, R_block, K=K, seed=0,
+                             counter=5)
+    ref = pist[:, 1:] - pist[:, :1]
+    report(f"diff piston p{precision}", host(out), ref, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("R,R_block", [(500, 500), (500, 64), (60, 1)])
+def test_diff_piston_structure_parity(q, ctx, precision, R, R_block):
+    cfg = workloads.diffpiston()
+    K = 700
+    n_sets = math.ceil(R / R_block)
+    s = q.logpolar_sampler(cfg["fmin"], cfg["fmax"], index=1234)
+    sf, se = ctx.diff_piston_structure(q.psd(0.1, 25.0), q.Aperture(cfg["D"], 0.0),
+                                       dev(cfg["bx"]), dev(cfg["by"]), s, K, R, R_block,
+                                       rng=q.Rng(9, 0, 0), precision=precision)
+    assert s.index == 1234 + n_sets * K
+    fx, fy, area = oracle.sample_logpolar(n_sets, K, cfg["fmin"], cfg["fmax"], index=1234)
+    w = oracle.weights(fx, fy, area, r0=0.1, L0=25.0, D=cfg["D"])
+    rsf, rse = oracle.diff_piston_sf(fx, fy, w, cfg["bx"], cfg["by"], R, R_block, K=K, seed=9)
+    tol = {0: 1e-10, 1: 2e-5, 2: 2e-3}[precision]
+    g, gs = host(sf), host(se)
+    print(f"sf p{precision} R{R} Rb{R_block}: max rel {np.max(np.abs(g / rsf - 1)):.3e}")
+    assert np.max(np.abs(g / rsf - 1)) < tol
+    assert np.max(np.abs(gs / rse - 1)) < 20 * tol
+
+
+def test_diff_piston_structure_deterministic(q, ctx):
+    cfg = workloads.diffpiston()
+    outs = []
+    for _ in range(2):
+        s = q.logpolar_sampler(cfg["fmin"], cfg["fmax"])
+        sf, _ = ctx.diff_piston_structure(q.psd(0.1, 25.0), q.Aperture(1.8, 0.0), dev(cfg["bx"]),
+                                          dev(cfg["by"]), s, 2048, 3000, 256,
+                                          rng=q.Rng(0, 0, 0), precision=1)
+        outs.append(host(sf))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_diff_piston_structure_full_size(q, ctx):
+    """The 1e5-realisation, K = 16384 differential-piston workload in the
+    launch configuration the benchmark times: (a) the fused structure-function
+    sums equal the squares of the stored differential pistons; (b) sampled
+    realisations of those pistons equal the oracle's; (c) the estimate agrees
+    with the analytic curve within its statistical error."""
+    from oracle import analytic as A
+    cfg = workloads.diffpiston()
+    K, R, R_block = cfg["K"], cfg["R"], 256
+    n_sets = math.ceil(R / R_block)
+    p = q.psd(cfg["r0"], 25.0)
+    ap = q.Aperture(cfg["D"], 0.0)
+    bx, by = dev(cfg["bx"]), dev(cfg["by"])
+    s = q.logpolar_sampler(cfg["fmin"], cfg["fmax"])
+    sf, se = ctx.diff_piston_structure(p, ap, bx, by, s, K, R, R_block, rng=q.Rng(0, 0, 0),
+                                       precision=1)
+    # same frequency sets and coefficients through the storing kernel
+    s2 = q.logpolar_sampler(cfg["fmin"], cfg["fmax"])
+    fx, fy, area = ctx.sample_frequencies(s2, n_sets, K)
+    w = ctx.weights(p, fx, fy, area, ap)
+    dp = ctx.diff_piston(K, fx, fy, w, bx, by, R, R_block, rng=q.Rng(0, 0, 0), precision=1)
+    dph = host(dp)
+    mean_sq = np.mean(dph * dph, axis=0)
+    assert np.max(np.abs(host(sf) / mean_sq - 1)) < 1e-6
+    # sampled realisations against the oracle
+    hfx, hfy, hw = host(fx), host(fy), host(w)
+    for r in (0, 255, 256, 54321, R - 1):
+        sidx = r // R_block
+        sl = slice(sidx * K, (sidx + 1) * K)
+        px = np.concatenate([[0.0], cfg["bx"]])
+        py = np.concatenate([[0.0], cfg["by"]])
+        pist = oracle.synthesize(hfx[sl], hfy[sl], hw[sl], px, py, 1, 1, K=K, seed=0, counter=r)
+        ref = pist[0, 1:] - pist[0, 0]
+        e = np.max(np.abs(dph[r] - ref)) / math.sqrt(np.mean(ref * ref))
+        print(f"row {r}: eps_max {e:.3e}")
+        assert e < 1e-5
+    # statistics: agreement with the band-limited analytic curve
+    an = A.sf_band(cfg["bx"], cfg["r0"], 25.0, cfg["fmin"], cfg["fmax"], D=cfg["D"])
+    z = (host(sf) - an) / host(se)
+    print("z", np.round(z, 2))
+    assert np.all(np.abs(z) < 4.5)
+
+
+# -------------------------------------------------------------- errors ----
+
+def test_invalid_arguments_raise(q, ctx):
+    fx = dev(np.zeros(10))
+    with pytest.raises(q.QrfsError) as e:
+        ctx.synthesize_phase(10, fx, fx, fx, fx, fx, 5, 6)  # R_block > R
+    assert e.value.status == q.ERR_INVALID_ARG
+    with pytest.raises(q.QrfsError) as e:
+        ctx.weights(q.psd(-0.1, 25.0), fx, fx, fx)
+    assert e.value.status == q.ERR_INVALID_ARG
+    with pytest.raises(q.QrfsError) as e:
+        ctx.sample_frequencies(q.logpolar_sampler(1.0, 0.5), 1, 10)
+    assert e.value.status == q.ERR_INVALID_ARG
+    s = q.logpolar_sampler(1e-3, 1e2)
+    s.scheme = q.SAMPLER_LEARNED
+    with pytest.raises(q.QrfsError) as e:
+        ctx.sample_frequencies(s, 1, 10)
+    assert e.value.status == q.ERR_UNSUPPORTED

@@ -253,7 +253,7 @@ def test_gaussian_coefficients_block_layout():
     seed, r = 0x1234567890ABCDEF, 77
     c = oracle.coefficients(seed, r, 6)
     x = oracle.philox4x32_10([1, r, 0, 0], [seed & 0xFFFFFFFF, seed >> 32])
-    u = ((x >> 8).astype(np.float64) + 0.5) * 2.0 ** -24
+    u = ((x >> 9).astype(np.float64) + 0.5) * 2.0 ** -23
     rho = math.sqrt(-2 * math.log(u[0]))
     assert c[4] == pytest.approx(rho * math.cos(2 * math.pi * u[1]), rel=1e-14)
     assert c[5] == pytest.approx(rho * math.sin(2 * math.pi * u[1]), rel=1e-14)
@@ -338,7 +338,7 @@ def test_eq3_mode_is_eq3():
         acc = 0.0
         for k in range(K):
             x = oracle.philox4x32_10([k, r, 0, 0], key)
-            u = ((x >> 8).astype(np.float64) + 0.5) * 2.0 ** -24
+            u = ((x >> 9).astype(np.float64) + 0.5) * 2.0 ** -23
             Rn = math.sqrt(-2 * math.log(u[0])) * math.cos(2 * math.pi * u[1])
             Ru = u[2]
             acc += 2 / math.sqrt(2) * Rn * w[k] * math.cos(
