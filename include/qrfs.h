@@ -231,6 +231,21 @@ QRFS_API qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_ps
                                        int64_t R_block, const qrfs_rng* rng, int32_t precision,
                                        double* sf, double* sf_stderr, void* stream);
 
+/* Differential-piston structure function for caller-supplied frequency
+ * sets: the same sums as qrfs_diff_piston_structure without the sampling and
+ * weighting steps.  fx, fy, w: double[n_sets][K] (n_sets = ceil(R/R_block)),
+ * w carrying the aperture filter; bx, by: double[nB]; sf, sf_stderr:
+ * double[nB] (sf_stderr may be NULL); all device.  Errors as
+ * qrfs_synthesize_phase. */
+QRFS_API qrfs_status qrfs_diff_piston_structure_sets(qrfs_context* ctx, int64_t K,
+                                                     const double* fx, const double* fy,
+                                                     const double* w, int64_t nB,
+                                                     const double* bx, const double* by,
+                                                     int64_t R, int64_t R_block,
+                                                     const qrfs_rng* rng, int32_t precision,
+                                                     double* sf, double* sf_stderr,
+                                                     void* stream);
+
 #ifdef __cplusplus
 }
 #endif

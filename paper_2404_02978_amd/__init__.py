@@ -107,6 +107,8 @@ def load_library():
                             ctypes.POINTER(Rng), _P, _I32, _P, _P]),
         "qrfs_diff_piston": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _I64, _I64,
                                  ctypes.POINTER(Rng), _P, _I32, _P, _P]),
+        "qrfs_diff_piston_structure_sets": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _I64, _I64,
+                                                ctypes.POINTER(Rng), _I32, _P, _P, _P]),
         "qrfs_diff_piston_structure": (S, [_P, ctypes.POINTER(Psd), ctypes.POINTER(Aperture), _I64,
                                            _P, _P, ctypes.POINTER(Sampler), _I64, _I64, _I64,
                                            ctypes.POINTER(Rng), _I32, _P, _P, _P]),
@@ -257,4 +259,21 @@ class Context:
             self._h, ctypes.byref(psd_), ctypes.byref(aperture), nB, _dev_f64(bx, "bx"),
             _dev_f64(by, "by", nB), ctypes.byref(sampler), K, R, R_block, ctypes.byref(rng),
             precision, _ptr(sf), _ptr(se), _stream()))
+        return sf, se
+
+    def diff_piston_structure_sets(self, K, fx, fy, w, bx, by, R, R_block, rng=None,
+                                   precision=PREC_FP32, with_stderr=True, sf=None, se=None):
+        """Structure function from caller-supplied frequency sets (w carries
+        the aperture filter).  Returns (sf, stderr) float64 [nB] on the device."""
+        n_sets = math.ceil(R / R_block)
+        nB = bx.numel()
+        sf = torch.empty(nB, dtype=torch.float64, device=self.device) if sf is None else sf
+        if with_stderr and se is None:
+            se = torch.empty_like(sf)
+        rng = rng if rng is not None else Rng(0, 0, COEF_GAUSS_CS)
+        _check(load_library().qrfs_diff_piston_structure_sets(
+            self._h, K, _dev_f64(fx, "fx", n_sets * K), _dev_f64(fy, "fy", n_sets * K),
+            _dev_f64(w, "w", n_sets * K), nB, _dev_f64(bx, "bx"), _dev_f64(by, "by", nB), R,
+            R_block, ctypes.byref(rng), precision, _ptr(sf), _ptr(se if with_stderr else None),
+            _stream()))
         return sf, se

@@ -413,4 +413,50 @@ qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
     return ok();
 }
 
+qrfs_status qrfs_diff_piston_structure_sets(qrfs_context* ctx, int64_t K, const double* fx,
+                                            const double* fy, const double* w, int64_t nB,
+                                            const double* bx, const double* by, int64_t R,
+                                            int64_t R_block, const qrfs_rng* rng,
+                                            int32_t precision, double* sf, double* sf_stderr,
+                                            void* stream) {
+    qrfs_status st = check_sum_common(K, nB, R, R_block, rng, nullptr, precision);
+    if (st) return st;
+    CHECK_PTR(fx);
+    CHECK_PTR(fy);
+    CHECK_PTR(w);
+    CHECK_PTR(bx);
+    CHECK_PTR(by);
+    CHECK_PTR(sf);
+    if (sf_stderr && !aligned8(sf_stderr))
+        return fail(QRFS_ERR_INVALID_ARG, "sf_stderr is not 8-byte aligned");
+    if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
+    const int64_t n_sets = cdiv(R, R_block);
+    const int64_t rts = qrfs::sum_row_tiles_per_set(precision, qrfs::BASIS_DIFF, R_block, nB);
+    const size_t partial_bytes = align256((size_t)(n_sets * rts * nB) * 2 * sizeof(double));
+    if ((st = ensure_workspace(ctx, partial_bytes))) return st;
+    qrfs::SumArgs a{};
+    a.K = K;
+    a.fx = fx;
+    a.fy = fy;
+    a.w = w;
+    a.P = nB;
+    a.px = bx;
+    a.py = by;
+    a.R = R;
+    a.R_block = R_block;
+    a.seed = rng->seed;
+    a.counter = rng->counter;
+    a.mode = rng->mode;
+    a.partial = (double*)ctx->ws;
+    if ((st = run_sum(precision, qrfs::BASIS_DIFF, qrfs::EPI_SFSUM, a, n_sets,
+                      (hipStream_t)stream)))
+        return st;
+    hipError_t e = qrfs::launch_reduce_sf((double*)ctx->ws, n_sets * rts, nB, R, sf, sf_stderr,
+                                          (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "reduction launch");
+    return ok();
+}
+
 }  // extern "C"

@@ -80,7 +80,9 @@ __device__ __forceinline__ void sincos2pi_unit_f32(float u, float& s, float& c) 
 // Box-Muller on binary32: (u1, u2) -> rho (cos 2 pi u2, sin 2 pi u2),
 // rho = sqrt(-2 ln u1) = sqrt(-2 ln2 log2 u1).
 __device__ __forceinline__ void box_muller_f32(float u1, float u2, float& g0, float& g1) {
-    float rho = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+    // the argument lies in [1.2e-7, 33.3] (normal), where the raw
+    // v_sqrt_f32 is within 1 ulp
+    float rho = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
     float s, c;
     sincos2pi_unit_f32(u2, s, c);
     g0 = rho * c;

@@ -221,23 +221,28 @@ __global__ __launch_bounds__(256) void k_sum_f64(SumArgs a, int64_t row_tiles,
 // lane draws exactly the coefficients its own MFMA A-operand needs (no LDS
 // traffic for coefficients) while the basis tile is shared through LDS.
 //
-// Per chunk of KC = 16 frequencies:
-//   - the block evaluates the basis: t = f.x in FP64, r = t - rint(t),
-//     hardware sin/cos of 2 pi r in FP32, times the weight (and the
-//     aperture filter for pistons); stored as [column][2 KC] floats (FP32)
-//     or as bf16 hi and lo planes (split-BF16);
-//   - FP32: 16 steps of v_mfma_f32_32x32x2_f32.  Lane (r, h) holds the 4
+// Per chunk of KC = 32 frequencies:
+//   - every thread evaluates the basis for one frequency (the next chunk's
+//     f, w are prefetched into registers one chunk ahead) and a few
+//     columns: t = f.x in FP64, r = t - rint(t), hardware sin/cos of 2 pi r
+//     in FP32, times the weight (and the aperture filter for pistons);
+//     stored as [column][2 KC] floats (FP32) or as bf16 hi and lo planes
+//     (split-BF16) in one of two LDS buffers, so one barrier per chunk
+//     suffices;
+//   - each lane then draws all Philox blocks of the chunk before any MFMA
+//     (independent integer chains the scheduler can interleave);
+//   - FP32: 32 steps of v_mfma_f32_32x32x2_f32.  Lane (r, h) holds the 4
 //     coefficients of Philox block t = k0/2 + 2m + h, so step (m, q) uses
 //     chunk-local contraction index j = 8m + 4h + q on both operands (the
 //     contraction order is permuted, the result is not);
-//   - split-BF16: 2 steps of v_mfma_f32_32x32x16_bf16 x 3 (hi.hi, hi.lo,
+//   - split-BF16: 4 steps of v_mfma_f32_32x32x16_bf16 x 3 (hi.hi, hi.lo,
 //     lo.hi).  Lane (r, h) holds coefficients j = 16 s + 8 h + 0..7, the
 //     natural order.
 // The MFMA accumulators are added to a second FP32 accumulator every FLUSH
 // chunks (64 frequencies), which keeps the rounding error of long sums at
 // ~u (sqrt(64) + sqrt(K/64)) instead of ~u sqrt(K).
-constexpr int KC = 16;
-constexpr int FLUSH = 4;
+constexpr int KC = 32;
+constexpr int FLUSH = 2;
 constexpr int STR_F32 = 2 * KC + 4;   // floats per basis column (16-byte rows, skewed banks)
 constexpr int STR_BF16 = 2 * KC + 8;  // bf16 per basis column
 
@@ -257,18 +262,37 @@ __device__ __forceinline__ void basis_pair(double t, double amp, float& cb, floa
     sb *= fa;
 }
 
-template <int PREC, int BASIS, int EPI, int MW, int NB>
+// CSRC: coefficient source, 0 = Gaussian cos/sin from Philox, 1 = Eq. 3
+// form from Philox, 2 = caller-supplied array (compile-time, so the integer
+// generator of the unused mode never reaches the instruction stream).
+template <int CSRC>
+__device__ __forceinline__ void coef4_src(const SumArgs& a, int64_t row, bool rowok, uint32_t t,
+                                          float g[4]) {
+    if constexpr (CSRC == 2) {
+        const int64_t twoK = 2 * a.K;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int64_t j = 4 * (int64_t)t + q;
+            g[q] = (rowok && j < twoK) ? (float)a.coef[row * twoK + j] : 0.0f;
+        }
+    } else {
+        if constexpr (CSRC == 0) gauss4_f32(a.seed, a.counter + (uint64_t)row, t, g);
+        else coef4_f32(a.seed, a.counter + (uint64_t)row, t, 1, g);
+        if (!rowok) g[0] = g[1] = g[2] = g[3] = 0.0f;
+    }
+}
+
+template <int PREC, int BASIS, int EPI, int MW, int NB, int CSRC>
 __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
                                                   int64_t col_tiles) {
     constexpr int NT = 32 * NB;
-    constexpr int NBF = PREC == 1 ? NT * STR_F32 : 4;
-    constexpr int NBH = PREC == 2 ? NT * STR_BF16 : 8;
+    constexpr int NBF = PREC == 1 ? 2 * NT * STR_F32 : 4;
+    constexpr int NBH = PREC == 2 ? 2 * NT * STR_BF16 : 8;
     __shared__ __attribute__((aligned(16))) float sBf[NBF];
     __shared__ __attribute__((aligned(16))) __bf16 sBh[NBH];
     __shared__ __attribute__((aligned(16))) __bf16 sBl[NBH];
-    __shared__ double sfx[KC], sfy[KC], sw[KC];
-    __shared__ double spx[NT], spy[NT], sD[NT], sd[NT];
     __shared__ double sred[4][NT][2];
+    __shared__ double spx[NT], spy[NT], sD[NT], sd[NT];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -279,6 +303,11 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
     const TileInfo ti = decode_tile(a, row_tiles, col_tiles, MT);
     const int64_t col0 = ti.ct * NT;
 
+    // basis work of this thread: frequency kk of every chunk, columns
+    // pp0 + j * cstep
+    const int kk = threadIdx.x % KC;
+    const int pp0 = threadIdx.x / KC;
+    const int cstep = blockDim.x / KC;
     for (int i = threadIdx.x; i < NT; i += blockDim.x) {
         int64_t p = col0 + i;
         bool ok = p < a.P;
@@ -289,6 +318,7 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
             sd[i] = ok ? a.apd[p] : 0.0;
         }
     }
+    __syncthreads();
 
     int64_t myrow[MW];
     bool rowok[MW];
@@ -300,7 +330,6 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
     const double* fx = a.fx + ti.sl * a.K;
     const double* fy = a.fy + ti.sl * a.K;
     const double* w = a.w + ti.sl * a.K;
-    const int64_t twoK = 2 * a.K;
 
     f32x16 acc[MW][NB];
     f32x16 mst[MW][NB];
@@ -316,65 +345,69 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
         }
 
     const int64_t nchunks = (a.K + KC - 1) / KC;
+    // frequency data of chunk 0 for this thread's kk
+    double nfx = 0.0, nfy = 0.0, nw = 0.0;
+    if (kk < a.K) {
+        nfx = fx[kk];
+        nfy = fy[kk];
+        nw = w[kk];
+    }
     for (int64_t ch = 0; ch < nchunks; ++ch) {
         const int64_t k0 = ch * KC;
-        __syncthreads();
-        if (threadIdx.x < KC) {
-            int64_t k = k0 + threadIdx.x;
-            bool ok = k < a.K;
-            sfx[threadIdx.x] = ok ? fx[k] : 0.0;
-            sfy[threadIdx.x] = ok ? fy[k] : 0.0;
-            sw[threadIdx.x] = ok ? w[k] : 0.0;
-        }
-        __syncthreads();
-        // basis tile: frequency index fastest so neighbouring threads write
-        // neighbouring LDS words
-        for (int i = threadIdx.x; i < KC * NT; i += blockDim.x) {
-            const int kk = i % KC;
-            const int pp = i / KC;
-            double t = sfx[kk] * spx[pp] + sfy[kk] * spy[pp];
-            double amp = sw[kk];
-            if (BASIS == BASIS_PISTON)
-                amp *= aperture_filter(sD[pp], sd[pp], sqrt(sfx[kk] * sfx[kk] + sfy[kk] * sfy[kk]));
-            float cb, sb;
-            basis_pair<PREC, BASIS>(t, amp, cb, sb);
-            if (PREC == 1) {
-                sBf[pp * STR_F32 + 2 * kk] = cb;
-                sBf[pp * STR_F32 + 2 * kk + 1] = sb;
+        const int buf = (int)(ch & 1);
+        const double cfx = nfx, cfy = nfy, cw = nw;
+        {
+            int64_t kn = k0 + KC + kk;
+            if (kn < a.K) {
+                nfx = fx[kn];
+                nfy = fy[kn];
+                nw = w[kn];
             } else {
-                __bf16 ch_ = (__bf16)cb;
-                __bf16 sh_ = (__bf16)sb;
-                sBh[pp * STR_BF16 + 2 * kk] = ch_;
-                sBh[pp * STR_BF16 + 2 * kk + 1] = sh_;
-                sBl[pp * STR_BF16 + 2 * kk] = (__bf16)(cb - (float)ch_);
-                sBl[pp * STR_BF16 + 2 * kk + 1] = (__bf16)(sb - (float)sh_);
+                nfx = nfy = nw = 0.0;
             }
         }
-        __syncthreads();
+        // basis of this chunk into buffer `buf`
+        const double fmag = BASIS == BASIS_PISTON ? sqrt(cfx * cfx + cfy * cfy) : 0.0;
+        for (int pp = pp0; pp < NT; pp += cstep) {
+            {
+                double amp = cw;
+                if (BASIS == BASIS_PISTON) amp *= aperture_filter(sD[pp], sd[pp], fmag);
+                float cb, sb;
+                basis_pair<PREC, BASIS>(cfx * spx[pp] + cfy * spy[pp], amp, cb, sb);
+                if (PREC == 1) {
+                    float* dst = sBf + buf * NT * STR_F32 + pp * STR_F32 + 2 * kk;
+                    dst[0] = cb;
+                    dst[1] = sb;
+                } else {
+                    const int o = buf * NT * STR_BF16 + pp * STR_BF16 + 2 * kk;
+                    __bf16 ch_ = (__bf16)cb;
+                    __bf16 sh_ = (__bf16)sb;
+                    sBh[o] = ch_;
+                    sBh[o + 1] = sh_;
+                    sBl[o] = (__bf16)(cb - (float)ch_);
+                    sBl[o + 1] = (__bf16)(sb - (float)sh_);
+                }
+            }
+        }
 
         if (PREC == 1) {
+            // coefficients of the whole chunk: KC/4 Philox blocks per row block
+            float av[KC / 4][MW][4];
 #pragma unroll
             for (int m = 0; m < KC / 4; ++m) {
                 const uint32_t t = (uint32_t)(k0 / 2) + 2u * m + (uint32_t)lh;
-                float av[MW][4];
 #pragma unroll
-                for (int mw = 0; mw < MW; ++mw) {
-                    if (a.coef) {
+                for (int mw = 0; mw < MW; ++mw)
+                    coef4_src<CSRC>(a, myrow[mw], rowok[mw], t, av[m][mw]);
+            }
+            __syncthreads();
+            const float* B = sBf + buf * NT * STR_F32;
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            int64_t j = 4 * (int64_t)t + q;
-                            av[mw][q] = (rowok[mw] && j < twoK) ? (float)a.coef[myrow[mw] * twoK + j]
-                                                                : 0.0f;
-                        }
-                    } else {
-                        coef4_f32(a.seed, a.counter + (uint64_t)myrow[mw], t, a.mode, av[mw]);
-                        if (!rowok[mw]) av[mw][0] = av[mw][1] = av[mw][2] = av[mw][3] = 0.0f;
-                    }
-                }
+            for (int m = 0; m < KC / 4; ++m) {
                 f32x4 bv[NB];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
-                    bv[nb] = *(const f32x4*)&sBf[(nb * 32 + lr) * STR_F32 + 8 * m + 4 * lh];
+                    bv[nb] = *(const f32x4*)&B[(nb * 32 + lr) * STR_F32 + 8 * m + 4 * lh];
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -382,46 +415,39 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
 #pragma unroll
                         for (int nb = 0; nb < NB; ++nb)
                             acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                                av[mw][q], bv[nb][q], acc[mw][nb], 0, 0, 0);
+                                av[m][mw][q], bv[nb][q], acc[mw][nb], 0, 0, 0);
             }
         } else {
+            bf16x8 ah[KC / 8][MW], al[KC / 8][MW];
 #pragma unroll
             for (int sg = 0; sg < KC / 8; ++sg) {
                 const uint32_t t = (uint32_t)(k0 / 2) + 4u * sg + 2u * (uint32_t)lh;
-                bf16x8 ah[MW], al[MW];
 #pragma unroll
                 for (int mw = 0; mw < MW; ++mw) {
                     float g[8];
-                    if (a.coef) {
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) {
-                            int64_t j = 4 * (int64_t)t + q;
-                            g[q] = (rowok[mw] && j < twoK) ? (float)a.coef[myrow[mw] * twoK + j] : 0.0f;
-                        }
-                    } else {
-                        coef4_f32(a.seed, a.counter + (uint64_t)myrow[mw], t, a.mode, g);
-                        coef4_f32(a.seed, a.counter + (uint64_t)myrow[mw], t + 1u, a.mode, g + 4);
-                        if (!rowok[mw])
-#pragma unroll
-                            for (int q = 0; q < 8; ++q) g[q] = 0.0f;
-                    }
+                    coef4_src<CSRC>(a, myrow[mw], rowok[mw], t, g);
+                    coef4_src<CSRC>(a, myrow[mw], rowok[mw], t + 1u, g + 4);
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
                         __bf16 hi = (__bf16)g[q];
-                        ah[mw][q] = hi;
-                        al[mw][q] = (__bf16)(g[q] - (float)hi);
+                        ah[sg][mw][q] = hi;
+                        al[sg][mw][q] = (__bf16)(g[q] - (float)hi);
                     }
                 }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int sg = 0; sg < KC / 8; ++sg) {
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const int off = (nb * 32 + lr) * STR_BF16 + 16 * sg + 8 * lh;
+                    const int off = buf * NT * STR_BF16 + (nb * 32 + lr) * STR_BF16 + 16 * sg + 8 * lh;
                     bf16x8 bh = *(const bf16x8*)&sBh[off];
                     bf16x8 bl = *(const bf16x8*)&sBl[off];
 #pragma unroll
                     for (int mw = 0; mw < MW; ++mw) {
-                        acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mw], bh, acc[mw][nb], 0, 0, 0);
-                        acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mw], bl, acc[mw][nb], 0, 0, 0);
-                        acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[mw], bh, acc[mw][nb], 0, 0, 0);
+                        acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[sg][mw], bh, acc[mw][nb], 0, 0, 0);
+                        acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[sg][mw], bl, acc[mw][nb], 0, 0, 0);
+                        acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[sg][mw], bh, acc[mw][nb], 0, 0, 0);
                     }
                 }
             }
@@ -563,14 +589,15 @@ struct MfmaShape {
     int MW, NB, WV;
 };
 
-static MfmaShape mfma_shape(int basis, int64_t R_block, int64_t P) {
+static MfmaShape mfma_shape(int precision, int basis, int64_t R_block, int64_t P) {
     MfmaShape s;
-    if (basis == BASIS_PHASE && P > 32) {
-        s.MW = 2;
-        s.NB = 2;
-    } else {
+    const bool wide = basis == BASIS_PHASE && P > 32;
+    if (precision == 1) {  // FP32: one 32-row block per wave keeps 4 waves/SIMD
         s.MW = 1;
-        s.NB = 1;
+        s.NB = wide ? 2 : 1;
+    } else {               // split-BF16: the A operand is reused over 2x2 blocks
+        s.MW = wide ? 2 : 1;
+        s.NB = wide ? 2 : 1;
     }
     int64_t wv = cdiv(R_block, 32 * s.MW);
     s.WV = (int)(wv > 4 ? 4 : wv);
@@ -579,7 +606,7 @@ static MfmaShape mfma_shape(int basis, int64_t R_block, int64_t P) {
 
 int64_t sum_row_tiles_per_set(int precision, int basis, int64_t R_block, int64_t P) {
     if (precision == 0) return cdiv(R_block, F64_TR);
-    MfmaShape s = mfma_shape(basis, R_block, P);
+    MfmaShape s = mfma_shape(precision, basis, R_block, P);
     return cdiv(R_block, 32 * s.MW * s.WV);
 }
 
@@ -599,16 +626,29 @@ static hipError_t launch_mfma_t(const SumArgs& a, int WV, hipStream_t st) {
     int64_t row_tiles = cdiv(a.R_block, MT);
     int64_t col_tiles = cdiv(a.P, 32 * NB);
     int64_t blocks = (a.set1 - a.set0) * row_tiles * col_tiles;
-    hipLaunchKernelGGL((k_sum_mfma<PREC, BASIS, EPI, MW, NB>), dim3((unsigned)blocks),
-                       dim3(64 * WV), 0, st, a, row_tiles, col_tiles);
+    dim3 g((unsigned)blocks), b(64 * WV);
+    if (a.coef)
+        hipLaunchKernelGGL((k_sum_mfma<PREC, BASIS, EPI, MW, NB, 2>), g, b, 0, st, a, row_tiles,
+                           col_tiles);
+    else if (a.mode == 1)
+        hipLaunchKernelGGL((k_sum_mfma<PREC, BASIS, EPI, MW, NB, 1>), g, b, 0, st, a, row_tiles,
+                           col_tiles);
+    else
+        hipLaunchKernelGGL((k_sum_mfma<PREC, BASIS, EPI, MW, NB, 0>), g, b, 0, st, a, row_tiles,
+                           col_tiles);
     return hipGetLastError();
 }
 
 template <int PREC, int BASIS, int EPI>
 static hipError_t launch_mfma(const SumArgs& a, hipStream_t st) {
-    MfmaShape s = mfma_shape(BASIS, a.R_block, a.P);
-    if (s.MW == 2) return launch_mfma_t<PREC, BASIS, EPI, 2, 2>(a, s.WV, st);
-    return launch_mfma_t<PREC, BASIS, EPI, 1, 1>(a, s.WV, st);
+    MfmaShape s = mfma_shape(PREC, BASIS, a.R_block, a.P);
+    if constexpr (PREC == 1) {
+        if (s.NB == 2) return launch_mfma_t<PREC, BASIS, EPI, 1, 2>(a, s.WV, st);
+        return launch_mfma_t<PREC, BASIS, EPI, 1, 1>(a, s.WV, st);
+    } else {
+        if (s.MW == 2) return launch_mfma_t<PREC, BASIS, EPI, 2, 2>(a, s.WV, st);
+        return launch_mfma_t<PREC, BASIS, EPI, 1, 1>(a, s.WV, st);
+    }
 }
 
 template <int BASIS, int EPI>

@@ -323,3 +323,23 @@ def test_invalid_arguments_raise(q, ctx):
     with pytest.raises(q.QrfsError) as e:
         ctx.sample_frequencies(s, 1, 10)
     assert e.value.status == q.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_diff_piston_structure_sets_equals_end_to_end(q, ctx, precision):
+    """The set-level entry gives bit-identical results to the end-to-end one
+    when handed the same frequency sets."""
+    cfg = workloads.diffpiston()
+    K, R, R_block = 1000, 700, 128
+    n_sets = math.ceil(R / R_block)
+    p, ap = q.psd(0.1, 10.0), q.Aperture(cfg["D"], 0.0)
+    bx, by = dev(cfg["bx"]), dev(cfg["by"])
+    s = q.logpolar_sampler(cfg["fmin"], cfg["fmax"], index=77)
+    sf, se = ctx.diff_piston_structure(p, ap, bx, by, s, K, R, R_block, rng=q.Rng(3, 9, 0),
+                                       precision=precision)
+    s2 = q.logpolar_sampler(cfg["fmin"], cfg["fmax"], index=77)
+    fx, fy, area = ctx.sample_frequencies(s2, n_sets, K)
+    w = ctx.weights(p, fx, fy, area, ap)
+    sf2, se2 = ctx.diff_piston_structure_sets(K, fx, fy, w, bx, by, R, R_block,
+                                              rng=q.Rng(3, 9, 0), precision=precision)
+    assert torch.equal(sf, sf2) and torch.equal(se, se2)
