@@ -150,10 +150,17 @@ typedef struct {
  *               output float.
  *   SPLIT_BF16  as FP32 but each operand is split into bf16 hi + lo and the
  *               contraction is hi.hi + hi.lo + lo.hi on bf16 MFMA with FP32
- *               accumulation; output float. */
+ *               accumulation (~16 significant bits); output float.
+ *   BF16X6      each operand split three ways into bf16 hi + mid + lo (24
+ *               significant bits) and six products (hi.hi, hi.mid, mid.hi,
+ *               hi.lo, mid.mid, lo.hi) on bf16 MFMA: FP32-class accuracy on
+ *               the matrix cores, which run concurrently with the vector ALU
+ *               that draws the coefficients (FP32 MFMA shares the vector
+ *               datapath and does not); output float. */
 #define QRFS_PREC_FP64 0
 #define QRFS_PREC_FP32 1
 #define QRFS_PREC_SPLIT_BF16 2
+#define QRFS_PREC_BF16X6 3
 
 /* ---------------------------------------------------------- entry points */
 

@@ -32,6 +32,7 @@ COEF_EQ3 = 1
 PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_SPLIT_BF16 = 2
+PREC_BF16X6 = 3
 SEED_HALF = 1 << 63
 
 

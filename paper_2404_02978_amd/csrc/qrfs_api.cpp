@@ -130,7 +130,7 @@ qrfs_status check_sum_common(int64_t K, int64_t P, int64_t R, int64_t R_block,
     if (K > ((int64_t)1 << 33))
         return fail(QRFS_ERR_INVALID_ARG, "K too large for the 32-bit Philox block counter");
     if (precision != QRFS_PREC_FP64 && precision != QRFS_PREC_FP32 &&
-        precision != QRFS_PREC_SPLIT_BF16)
+        precision != QRFS_PREC_SPLIT_BF16 && precision != QRFS_PREC_BF16X6)
         return fail(QRFS_ERR_INVALID_ARG, "unknown precision %d", precision);
     if (!coef) {
         if (!rng) return fail(QRFS_ERR_INVALID_ARG, "rng is NULL and no coefficients were given");
@@ -149,8 +149,8 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 qrfs_status run_sum(int precision, int basis, int epi, qrfs::SumArgs a, int64_t n_sets,
                     hipStream_t st) {
     int64_t rts = qrfs::sum_row_tiles_per_set(precision, basis, a.R_block, a.P);
-    int64_t cts = cdiv(a.P, 32);
-    int64_t per_set = rts * cts;
+    int64_t cts = qrfs::sum_col_tiles(precision, basis, a.R_block, a.P);
+    int64_t per_set = rts * cts * (a.ksplit > 1 ? a.ksplit : 1);
     int64_t max_sets = ((int64_t)1 << 30) / (per_set > 0 ? per_set : 1);
     if (max_sets < 1) return fail(QRFS_ERR_INVALID_ARG, "problem too large for one set");
     const double* fx0 = a.fx;
@@ -211,6 +211,9 @@ qrfs_status sum_entry(qrfs_context* ctx, int basis, int64_t K, const double* fx,
     a.coef = coef;
     a.out = out;
     a.partial = nullptr;
+    a.ksplit = 1;
+    a.kspan = K;
+    a.phi_part = nullptr;
     s = run_sum(precision, basis, qrfs::EPI_STORE, a, cdiv(R, R_block), (hipStream_t)stream);
     if (s) return s;
     return ok();
@@ -358,20 +361,24 @@ qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
 
     const int64_t n_sets = cdiv(R, R_block);
     const int64_t rts = qrfs::sum_row_tiles_per_set(precision, qrfs::BASIS_DIFF, R_block, nB);
-    const size_t partial_bytes = align256((size_t)(n_sets * rts * nB) * 2 * sizeof(double));
+    const qrfs::SfPlan plan = qrfs::sf_plan(precision, K, R, R_block, nB);
+    const size_t partial_bytes = align256((size_t)(plan.n_partial_tiles * nB) * 2 * sizeof(double));
+    const size_t phi_bytes = align256(plan.phi_floats * sizeof(float));
     const size_t per_set = (size_t)K * 4 * sizeof(double);
     const size_t budget = (size_t)1 << 30;
     int64_t spb = (int64_t)(budget / per_set);
     if (spb < 1) spb = 1;
     if (spb > n_sets) spb = n_sets;
     const size_t arr = align256((size_t)spb * K * sizeof(double));
-    if ((st = ensure_workspace(ctx, partial_bytes + 4 * arr))) return st;
+    if ((st = ensure_workspace(ctx, partial_bytes + phi_bytes + 4 * arr))) return st;
     char* base = (char*)ctx->ws;
     double* partial = (double*)base;
-    double* fx = (double*)(base + partial_bytes);
-    double* fy = (double*)(base + partial_bytes + arr);
-    double* area = (double*)(base + partial_bytes + 2 * arr);
-    double* w = (double*)(base + partial_bytes + 3 * arr);
+    float* phi = (float*)(base + partial_bytes);
+    char* fbase = base + partial_bytes + phi_bytes;
+    double* fx = (double*)(fbase);
+    double* fy = (double*)(fbase + arr);
+    double* area = (double*)(fbase + 2 * arr);
+    double* w = (double*)(fbase + 3 * arr);
     hipStream_t stream_ = (hipStream_t)stream;
     const double c = psd->c > 0.0 ? psd->c : qrfs::kPsdConstant;
 
@@ -400,6 +407,9 @@ qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
         a.mode = rng->mode;
         a.coef = nullptr;
         a.out = nullptr;
+        a.ksplit = plan.ksplit;
+        a.kspan = plan.kspan;
+        a.phi_part = phi;
         // absolute set bounds; the batch buffers hold exactly these sets
         a.set0 = s0;
         a.set1 = s1;
@@ -407,7 +417,12 @@ qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
         e = qrfs::launch_sum(precision, qrfs::BASIS_DIFF, qrfs::EPI_SFSUM, a, stream_);
         if (e != hipSuccess) return hip_fail(e, "structure-function launch");
     }
-    hipError_t e = qrfs::launch_reduce_sf(partial, n_sets * rts, nB, R, sf, sf_stderr, stream_);
+    if (plan.ksplit > 1) {
+        hipError_t e = qrfs::launch_sfsum_rows(phi, plan.ksplit, R, nB, partial, stream_);
+        if (e != hipSuccess) return hip_fail(e, "split-K square launch");
+    }
+    hipError_t e = qrfs::launch_reduce_sf(partial, plan.n_partial_tiles, nB, R, sf, sf_stderr,
+                                          stream_);
     if (e != hipSuccess) return hip_fail(e, "reduction launch");
     s->index += (uint64_t)(n_sets * K);
     return ok();
@@ -433,9 +448,12 @@ qrfs_status qrfs_diff_piston_structure_sets(qrfs_context* ctx, int64_t K, const 
     DeviceGuard g(ctx->device);
     if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
     const int64_t n_sets = cdiv(R, R_block);
-    const int64_t rts = qrfs::sum_row_tiles_per_set(precision, qrfs::BASIS_DIFF, R_block, nB);
-    const size_t partial_bytes = align256((size_t)(n_sets * rts * nB) * 2 * sizeof(double));
-    if ((st = ensure_workspace(ctx, partial_bytes))) return st;
+    const qrfs::SfPlan plan = qrfs::sf_plan(precision, K, R, R_block, nB);
+    const size_t partial_bytes = align256((size_t)(plan.n_partial_tiles * nB) * 2 * sizeof(double));
+    const size_t phi_bytes = align256(plan.phi_floats * sizeof(float));
+    if ((st = ensure_workspace(ctx, partial_bytes + phi_bytes))) return st;
+    double* partial = (double*)ctx->ws;
+    float* phi = (float*)((char*)ctx->ws + partial_bytes);
     qrfs::SumArgs a{};
     a.K = K;
     a.fx = fx;
@@ -449,11 +467,18 @@ qrfs_status qrfs_diff_piston_structure_sets(qrfs_context* ctx, int64_t K, const 
     a.seed = rng->seed;
     a.counter = rng->counter;
     a.mode = rng->mode;
-    a.partial = (double*)ctx->ws;
+    a.partial = partial;
+    a.ksplit = plan.ksplit;
+    a.kspan = plan.kspan;
+    a.phi_part = phi;
     if ((st = run_sum(precision, qrfs::BASIS_DIFF, qrfs::EPI_SFSUM, a, n_sets,
                       (hipStream_t)stream)))
         return st;
-    hipError_t e = qrfs::launch_reduce_sf((double*)ctx->ws, n_sets * rts, nB, R, sf, sf_stderr,
+    if (plan.ksplit > 1) {
+        hipError_t e = qrfs::launch_sfsum_rows(phi, plan.ksplit, R, nB, partial, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "split-K square launch");
+    }
+    hipError_t e = qrfs::launch_reduce_sf(partial, plan.n_partial_tiles, nB, R, sf, sf_stderr,
                                           (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "reduction launch");
     return ok();

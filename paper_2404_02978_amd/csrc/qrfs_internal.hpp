@@ -43,12 +43,32 @@ struct SumArgs {
     int32_t mode;
     const double* coef;  // [R][2K] or nullptr
     void* out;           // EPI_STORE: float or double [R][P]
-    double* partial;     // EPI_SFSUM: [row tiles of this launch][P][2]
+    double* partial;     // EPI_SFSUM, ksplit == 1: [row tiles of this launch][P][2]
+    int32_t ksplit;      // frequency ranges per row tile (MFMA kernels, EPI_SFSUM)
+    int64_t kspan;       // frequencies per range (multiple of the chunk length)
+    float* phi_part;     // EPI_SFSUM, ksplit > 1: [ksplit][R][P] partial sums
 };
+
+// How the structure-function sums are split for a problem: ksplit
+// frequency ranges per row tile, the FP32 partial-sum buffer it needs, and
+// the number of partial rows the final reduction reads.
+struct SfPlan {
+    int ksplit;
+    int64_t kspan;
+    size_t phi_floats;
+    int64_t n_partial_tiles;
+};
+SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P);
+
+// squares of the K-range partial sums, summed per column over blocks of
+// rows: partial[ceil(R/256)][P][2]
+hipError_t launch_sfsum_rows(const float* phi, int ksplit, int64_t R, int64_t P, double* partial,
+                             hipStream_t st);
 
 // Row tiles one set occupies in `launch_sum` for this precision and R_block
 // (needed to size the partial-sum buffer).
 int64_t sum_row_tiles_per_set(int precision, int basis, int64_t R_block, int64_t P);
+int64_t sum_col_tiles(int precision, int basis, int64_t R_block, int64_t P);
 
 hipError_t launch_sum(int precision, int basis, int epi, const SumArgs& a, hipStream_t st);
 

@@ -220,33 +220,57 @@ __global__ __launch_bounds__(256) void k_sum_f64(SumArgs a, int64_t row_tiles,
 // [32 MW v, 32 MW (v+1)) of the tile and all NT = 32 NB columns, so each
 // lane draws exactly the coefficients its own MFMA A-operand needs (no LDS
 // traffic for coefficients) while the basis tile is shared through LDS.
+// A block covers the frequency range [ks * kspan, (ks + 1) * kspan) of its
+// rows (split K: several blocks per row tile keep the grid balanced when
+// the rows alone do not fill the chip evenly).
 //
 // Per chunk of KC = 32 frequencies:
 //   - every thread evaluates the basis for one frequency (the next chunk's
 //     f, w are prefetched into registers one chunk ahead) and a few
 //     columns: t = f.x in FP64, r = t - rint(t), hardware sin/cos of 2 pi r
 //     in FP32, times the weight (and the aperture filter for pistons);
-//     stored as [column][2 KC] floats (FP32) or as bf16 hi and lo planes
-//     (split-BF16) in one of two LDS buffers, so one barrier per chunk
+//     stored as [column][2 KC] floats (FP32) or as 16-bit hi and lo planes
+//     (split modes) in one of two LDS buffers, so one barrier per chunk
 //     suffices;
-//   - each lane then draws all Philox blocks of the chunk before any MFMA
-//     (independent integer chains the scheduler can interleave);
+//   - each lane then draws all Philox blocks of the chunk (independent
+//     integer chains the scheduler interleaves with the MFMAs);
 //   - FP32: 32 steps of v_mfma_f32_32x32x2_f32.  Lane (r, h) holds the 4
 //     coefficients of Philox block t = k0/2 + 2m + h, so step (m, q) uses
 //     chunk-local contraction index j = 8m + 4h + q on both operands (the
 //     contraction order is permuted, the result is not);
 //   - split-BF16: 4 steps of v_mfma_f32_32x32x16_bf16 x 3 (hi.hi, hi.lo,
-//     lo.hi).  Lane (r, h) holds coefficients j = 16 s + 8 h + 0..7, the
-//     natural order.
+//     lo.hi), ~16 significant bits.  BF16x6: operands split three ways
+//     (hi + mid + lo, 24 bits) and six products (hi.hi, hi.mid, mid.hi,
+//     hi.lo, mid.mid, lo.hi), FP32-class.  BF16 keeps the FP32 exponent
+//     range, so no operand is ever subnormal.  Lane (r, h) holds
+//     coefficients j = 16 s + 8 h + 0..7, the natural order.
+// FP32 MFMA runs on the vector datapath and never overlaps the VALU work of
+// the generator; the BF16 MFMAs run on the matrix cores and do.
 // The MFMA accumulators are added to a second FP32 accumulator every FLUSH
-// chunks (64 frequencies), which keeps the rounding error of long sums at
+// chunks, which keeps the rounding error of long sums at
 // ~u (sqrt(64) + sqrt(K/64)) instead of ~u sqrt(K).
 constexpr int KC = 32;
 constexpr int FLUSH = 2;
-constexpr int STR_F32 = 2 * KC + 4;   // floats per basis column (16-byte rows, skewed banks)
-constexpr int STR_BF16 = 2 * KC + 8;  // bf16 per basis column
+constexpr int STR_F32 = 2 * KC + 4;  // floats per basis column (16-byte rows, skewed banks)
+constexpr int STR_H = 2 * KC + 8;    // 16-bit values per basis column
 
-template <int PREC, int BASIS>
+__device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// x = hi + mid (+ lo) in bf16, each part the rounding of the remainder
+template <int NPL>
+__device__ __forceinline__ void split_bf16(float x, __bf16 part[NPL]) {
+    float r = x;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+        __bf16 h = (__bf16)r;
+        part[i] = h;
+        r -= (float)h;
+    }
+}
+
+template <int BASIS>
 __device__ __forceinline__ void basis_pair(double t, double amp, float& cb, float& sb) {
     float r = (float)frac_centered(t);
     if (BASIS == BASIS_DIFF) {
@@ -276,9 +300,11 @@ __device__ __forceinline__ void coef4_src(const SumArgs& a, int64_t row, bool ro
             g[q] = (rowok && j < twoK) ? (float)a.coef[row * twoK + j] : 0.0f;
         }
     } else {
+        // rows past the end of the set only feed output rows that are never
+        // stored or summed, so their (finite) coefficients need no masking;
+        // masking would split the Philox chains into separate basic blocks
         if constexpr (CSRC == 0) gauss4_f32(a.seed, a.counter + (uint64_t)row, t, g);
         else coef4_f32(a.seed, a.counter + (uint64_t)row, t, 1, g);
-        if (!rowok) g[0] = g[1] = g[2] = g[3] = 0.0f;
     }
 }
 
@@ -286,11 +312,11 @@ template <int PREC, int BASIS, int EPI, int MW, int NB, int CSRC>
 __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
                                                   int64_t col_tiles) {
     constexpr int NT = 32 * NB;
+    constexpr int NPL = PREC == 2 ? 2 : 3;  // bf16 planes per operand (split modes)
     constexpr int NBF = PREC == 1 ? 2 * NT * STR_F32 : 4;
-    constexpr int NBH = PREC == 2 ? 2 * NT * STR_BF16 : 8;
+    constexpr int NBH = PREC >= 2 ? 2 * NT * STR_H : 8;
     __shared__ __attribute__((aligned(16))) float sBf[NBF];
-    __shared__ __attribute__((aligned(16))) __bf16 sBh[NBH];
-    __shared__ __attribute__((aligned(16))) __bf16 sBl[NBH];
+    __shared__ __attribute__((aligned(16))) __bf16 sBp[NPL][NBH];
     __shared__ double sred[4][NT][2];
     __shared__ double spx[NT], spy[NT], sD[NT], sd[NT];
 
@@ -300,8 +326,21 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
     const int lr = lane & 31;
     const int lh = lane >> 5;
     const int64_t MT = 32 * MW * WV;
-    const TileInfo ti = decode_tile(a, row_tiles, col_tiles, MT);
-    const int64_t col0 = ti.ct * NT;
+
+    // tile: column tile fastest, then K split, row tile, set
+    int64_t bidx = blockIdx.x;
+    const int64_t ct = bidx % col_tiles;
+    bidx /= col_tiles;
+    const int64_t ks = bidx % a.ksplit;
+    bidx /= a.ksplit;
+    const int64_t rt = bidx % row_tiles;
+    const int64_t sl = bidx / row_tiles;
+    const int64_t set = a.set0 + sl;
+    const int64_t row_begin = set * a.R_block + rt * MT;
+    const int64_t row_end = (set + 1) * a.R_block < a.R ? (set + 1) * a.R_block : a.R;
+    const int64_t col0 = ct * NT;
+    const int64_t kb = ks * a.kspan;
+    const int64_t ke = kb + a.kspan < a.K ? kb + a.kspan : a.K;
 
     // basis work of this thread: frequency kk of every chunk, columns
     // pp0 + j * cstep
@@ -324,12 +363,12 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
     bool rowok[MW];
 #pragma unroll
     for (int mw = 0; mw < MW; ++mw) {
-        myrow[mw] = ti.row_begin + (int64_t)(wave * MW + mw) * 32 + lr;
-        rowok[mw] = myrow[mw] < ti.row_end;
+        myrow[mw] = row_begin + (int64_t)(wave * MW + mw) * 32 + lr;
+        rowok[mw] = myrow[mw] < row_end;
     }
-    const double* fx = a.fx + ti.sl * a.K;
-    const double* fy = a.fy + ti.sl * a.K;
-    const double* w = a.w + ti.sl * a.K;
+    const double* fx = a.fx + sl * a.K;
+    const double* fy = a.fy + sl * a.K;
+    const double* w = a.w + sl * a.K;
 
     f32x16 acc[MW][NB];
     f32x16 mst[MW][NB];
@@ -344,21 +383,21 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
             }
         }
 
-    const int64_t nchunks = (a.K + KC - 1) / KC;
-    // frequency data of chunk 0 for this thread's kk
+    const int64_t nchunks = (ke - kb + KC - 1) / KC;
+    // frequency data of the first chunk for this thread's kk
     double nfx = 0.0, nfy = 0.0, nw = 0.0;
-    if (kk < a.K) {
-        nfx = fx[kk];
-        nfy = fy[kk];
-        nw = w[kk];
+    if (kb + kk < ke) {
+        nfx = fx[kb + kk];
+        nfy = fy[kb + kk];
+        nw = w[kb + kk];
     }
     for (int64_t ch = 0; ch < nchunks; ++ch) {
-        const int64_t k0 = ch * KC;
+        const int64_t k0 = kb + ch * KC;
         const int buf = (int)(ch & 1);
         const double cfx = nfx, cfy = nfy, cw = nw;
         {
             int64_t kn = k0 + KC + kk;
-            if (kn < a.K) {
+            if (kn < ke) {
                 nfx = fx[kn];
                 nfy = fy[kn];
                 nw = w[kn];
@@ -369,28 +408,28 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
         // basis of this chunk into buffer `buf`
         const double fmag = BASIS == BASIS_PISTON ? sqrt(cfx * cfx + cfy * cfy) : 0.0;
         for (int pp = pp0; pp < NT; pp += cstep) {
-            {
-                double amp = cw;
-                if (BASIS == BASIS_PISTON) amp *= aperture_filter(sD[pp], sd[pp], fmag);
-                float cb, sb;
-                basis_pair<PREC, BASIS>(cfx * spx[pp] + cfy * spy[pp], amp, cb, sb);
-                if (PREC == 1) {
-                    float* dst = sBf + buf * NT * STR_F32 + pp * STR_F32 + 2 * kk;
-                    dst[0] = cb;
-                    dst[1] = sb;
-                } else {
-                    const int o = buf * NT * STR_BF16 + pp * STR_BF16 + 2 * kk;
-                    __bf16 ch_ = (__bf16)cb;
-                    __bf16 sh_ = (__bf16)sb;
-                    sBh[o] = ch_;
-                    sBh[o + 1] = sh_;
-                    sBl[o] = (__bf16)(cb - (float)ch_);
-                    sBl[o + 1] = (__bf16)(sb - (float)sh_);
+            double amp = cw;
+            if (BASIS == BASIS_PISTON) amp *= aperture_filter(sD[pp], sd[pp], fmag);
+            float cb, sb;
+            basis_pair<BASIS>(cfx * spx[pp] + cfy * spy[pp], amp, cb, sb);
+            if constexpr (PREC == 1) {
+                float* dst = sBf + buf * NT * STR_F32 + pp * STR_F32 + 2 * kk;
+                dst[0] = cb;
+                dst[1] = sb;
+            } else {
+                const int o = buf * NT * STR_H + pp * STR_H + 2 * kk;
+                __bf16 pc[NPL], ps[NPL];
+                split_bf16<NPL>(cb, pc);
+                split_bf16<NPL>(sb, ps);
+#pragma unroll
+                for (int i = 0; i < NPL; ++i) {
+                    sBp[i][o] = pc[i];
+                    sBp[i][o + 1] = ps[i];
                 }
             }
         }
 
-        if (PREC == 1) {
+        if constexpr (PREC == 1) {
             // coefficients of the whole chunk: KC/4 Philox blocks per row block
             float av[KC / 4][MW][4];
 #pragma unroll
@@ -418,7 +457,7 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
                                 av[m][mw][q], bv[nb][q], acc[mw][nb], 0, 0, 0);
             }
         } else {
-            bf16x8 ah[KC / 8][MW], al[KC / 8][MW];
+            bf16x8 ap[KC / 8][MW][NPL];
 #pragma unroll
             for (int sg = 0; sg < KC / 8; ++sg) {
                 const uint32_t t = (uint32_t)(k0 / 2) + 4u * sg + 2u * (uint32_t)lh;
@@ -429,9 +468,10 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
                     coef4_src<CSRC>(a, myrow[mw], rowok[mw], t + 1u, g + 4);
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
-                        __bf16 hi = (__bf16)g[q];
-                        ah[sg][mw][q] = hi;
-                        al[sg][mw][q] = (__bf16)(g[q] - (float)hi);
+                        __bf16 part[NPL];
+                        split_bf16<NPL>(g[q], part);
+#pragma unroll
+                        for (int i = 0; i < NPL; ++i) ap[sg][mw][i][q] = part[i];
                     }
                 }
             }
@@ -440,14 +480,23 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
             for (int sg = 0; sg < KC / 8; ++sg) {
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const int off = buf * NT * STR_BF16 + (nb * 32 + lr) * STR_BF16 + 16 * sg + 8 * lh;
-                    bf16x8 bh = *(const bf16x8*)&sBh[off];
-                    bf16x8 bl = *(const bf16x8*)&sBl[off];
+                    const int off = buf * NT * STR_H + (nb * 32 + lr) * STR_H + 16 * sg + 8 * lh;
+                    bf16x8 bp[NPL];
+#pragma unroll
+                    for (int i = 0; i < NPL; ++i) bp[i] = *(const bf16x8*)&sBp[i][off];
 #pragma unroll
                     for (int mw = 0; mw < MW; ++mw) {
-                        acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[sg][mw], bh, acc[mw][nb], 0, 0, 0);
-                        acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[sg][mw], bl, acc[mw][nb], 0, 0, 0);
-                        acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[sg][mw], bh, acc[mw][nb], 0, 0, 0);
+                        f32x16 c = acc[mw][nb];
+                        // smallest products first
+                        if constexpr (NPL == 3) {
+                            c = mfma_bf16(ap[sg][mw][2], bp[0], c);
+                            c = mfma_bf16(ap[sg][mw][1], bp[1], c);
+                            c = mfma_bf16(ap[sg][mw][0], bp[2], c);
+                        }
+                        c = mfma_bf16(ap[sg][mw][1], bp[0], c);
+                        c = mfma_bf16(ap[sg][mw][0], bp[1], c);
+                        c = mfma_bf16(ap[sg][mw][0], bp[0], c);
+                        acc[mw][nb] = c;
                     }
                 }
             }
@@ -474,8 +523,21 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
                 const int64_t col = col0 + nb * 32 + lr;
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
-                    int64_t r = ti.row_begin + (int64_t)(wave * MW + mw) * 32 + 8 * (i / 4) + 4 * lh + (i % 4);
-                    if (r < ti.row_end && col < a.P) out[r * a.P + col] = mst[mw][nb][i];
+                    int64_t r = row_begin + (int64_t)(wave * MW + mw) * 32 + 8 * (i / 4) + 4 * lh + (i % 4);
+                    if (r < row_end && col < a.P) out[r * a.P + col] = mst[mw][nb][i];
+                }
+            }
+    } else if (a.ksplit > 1) {
+        // partial sums of this frequency range; squared after all ranges are in
+#pragma unroll
+        for (int mw = 0; mw < MW; ++mw)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int64_t col = col0 + nb * 32 + lr;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    int64_t r = row_begin + (int64_t)(wave * MW + mw) * 32 + 8 * (i / 4) + 4 * lh + (i % 4);
+                    if (r < row_end && col < a.P) a.phi_part[(ks * a.R + r) * a.P + col] = mst[mw][nb][i];
                 }
             }
     } else {
@@ -486,8 +548,8 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
             for (int mw = 0; mw < MW; ++mw)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
-                    int64_t r = ti.row_begin + (int64_t)(wave * MW + mw) * 32 + 8 * (i / 4) + 4 * lh + (i % 4);
-                    if (r < ti.row_end) {
+                    int64_t r = row_begin + (int64_t)(wave * MW + mw) * 32 + 8 * (i / 4) + 4 * lh + (i % 4);
+                    if (r < row_end) {
                         double d = (double)mst[mw][nb][i];
                         double d2 = d * d;
                         s2 += d2;
@@ -510,11 +572,51 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
                     t2 += sred[v][c][0];
                     t4 += sred[v][c][1];
                 }
-                double* dst = a.partial + ((ti.sl * row_tiles + ti.rt) * a.P + col) * 2;
+                double* dst = a.partial + ((sl * row_tiles + rt) * a.P + col) * 2;
                 dst[0] = t2;
                 dst[1] = t4;
             }
         }
+    }
+}
+
+// ----------------------------------------------------- split-K squares ----
+// Block (row block rb, column tile): 256 threads = 8 row groups x 32
+// columns.  Adds the K-range partial sums of each differential piston in a
+// fixed order, then accumulates its square and fourth power per column over
+// the block's rows; the 8 row groups are combined in a fixed order.
+constexpr int SF_ROWS = 256;
+
+__global__ __launch_bounds__(256) void k_sfsum_rows(const float* __restrict__ phi, int ksplit,
+                                                    int64_t R, int64_t P,
+                                                    double* __restrict__ partial) {
+    __shared__ double r2[8][32], r4[8][32];
+    const int c = threadIdx.x & 31;
+    const int rg = threadIdx.x >> 5;
+    const int64_t col = (int64_t)blockIdx.y * 32 + c;
+    const int64_t r0 = (int64_t)blockIdx.x * SF_ROWS;
+    const int64_t r1 = r0 + SF_ROWS < R ? r0 + SF_ROWS : R;
+    double s2 = 0.0, s4 = 0.0;
+    if (col < P) {
+        for (int64_t r = r0 + rg; r < r1; r += 8) {
+            double v = 0.0;
+            for (int k = 0; k < ksplit; ++k) v += (double)phi[((int64_t)k * R + r) * P + col];
+            double v2 = v * v;
+            s2 += v2;
+            s4 += v2 * v2;
+        }
+    }
+    r2[rg][c] = s2;
+    r4[rg][c] = s4;
+    __syncthreads();
+    if (rg == 0 && col < P) {
+        double t2 = 0.0, t4 = 0.0;
+        for (int g = 0; g < 8; ++g) {
+            t2 += r2[g][c];
+            t4 += r4[g][c];
+        }
+        partial[((int64_t)blockIdx.x * P + col) * 2] = t2;
+        partial[((int64_t)blockIdx.x * P + col) * 2 + 1] = t4;
     }
 }
 
@@ -595,7 +697,7 @@ static MfmaShape mfma_shape(int precision, int basis, int64_t R_block, int64_t P
     if (precision == 1) {  // FP32: one 32-row block per wave keeps 4 waves/SIMD
         s.MW = 1;
         s.NB = wide ? 2 : 1;
-    } else {               // split-BF16: the A operand is reused over 2x2 blocks
+    } else {               // split modes: the A operand is reused over 2x2 blocks
         s.MW = wide ? 2 : 1;
         s.NB = wide ? 2 : 1;
     }
@@ -608,6 +710,36 @@ int64_t sum_row_tiles_per_set(int precision, int basis, int64_t R_block, int64_t
     if (precision == 0) return cdiv(R_block, F64_TR);
     MfmaShape s = mfma_shape(precision, basis, R_block, P);
     return cdiv(R_block, 32 * s.MW * s.WV);
+}
+
+int64_t sum_col_tiles(int precision, int basis, int64_t R_block, int64_t P) {
+    if (precision == 0) return cdiv(P, F64_TP);
+    MfmaShape s = mfma_shape(precision, basis, R_block, P);
+    return cdiv(P, 32 * s.NB);
+}
+
+SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P) {
+    SfPlan p;
+    const int64_t n_sets = cdiv(R, R_block);
+    const int64_t rts = sum_row_tiles_per_set(precision, BASIS_DIFF, R_block, P);
+    const int64_t cts = sum_col_tiles(precision, BASIS_DIFF, R_block, P);
+    const int64_t base = n_sets * rts * cts;
+    int64_t ks = 1;
+    if (precision != 0) {
+        // aim for >= 6 waves of blocks per resident slot (256 CUs x 4 blocks)
+        const int64_t target = 6 * 256 * 4;
+        const int64_t nch = cdiv(K, KC);
+        ks = cdiv(target, base);
+        if (ks > 16) ks = 16;
+        if (ks > nch / 2) ks = nch / 2;
+        if (ks < 1) ks = 1;
+        while (ks > 1 && (double)ks * R * P * 4.0 > (double)((size_t)1 << 30)) --ks;
+    }
+    p.ksplit = (int)ks;
+    p.kspan = cdiv(cdiv(K, ks), KC) * KC;  // whole chunks, even frequency offsets
+    p.phi_floats = ks > 1 ? (size_t)ks * R * P : 0;
+    p.n_partial_tiles = ks > 1 ? cdiv(R, SF_ROWS) : n_sets * rts;
+    return p;
 }
 
 template <int BASIS, int EPI>
@@ -625,7 +757,7 @@ static hipError_t launch_mfma_t(const SumArgs& a, int WV, hipStream_t st) {
     int64_t MT = 32 * MW * WV;
     int64_t row_tiles = cdiv(a.R_block, MT);
     int64_t col_tiles = cdiv(a.P, 32 * NB);
-    int64_t blocks = (a.set1 - a.set0) * row_tiles * col_tiles;
+    int64_t blocks = (a.set1 - a.set0) * row_tiles * col_tiles * a.ksplit;
     dim3 g((unsigned)blocks), b(64 * WV);
     if (a.coef)
         hipLaunchKernelGGL((k_sum_mfma<PREC, BASIS, EPI, MW, NB, 2>), g, b, 0, st, a, row_tiles,
@@ -655,7 +787,8 @@ template <int BASIS, int EPI>
 static hipError_t launch_be(int precision, const SumArgs& a, hipStream_t st) {
     if (precision == 0) return launch_f64<BASIS, EPI>(a, st);
     if (precision == 1) return launch_mfma<1, BASIS, EPI>(a, st);
-    return launch_mfma<2, BASIS, EPI>(a, st);
+    if (precision == 2) return launch_mfma<2, BASIS, EPI>(a, st);
+    return launch_mfma<3, BASIS, EPI>(a, st);
 }
 
 hipError_t launch_sum(int precision, int basis, int epi, const SumArgs& a, hipStream_t st) {
@@ -666,6 +799,13 @@ hipError_t launch_sum(int precision, int basis, int epi, const SumArgs& a, hipSt
         return launch_be<BASIS_DIFF, EPI_STORE>(precision, a, st);
     }
     return launch_be<BASIS_DIFF, EPI_SFSUM>(precision, a, st);
+}
+
+hipError_t launch_sfsum_rows(const float* phi, int ksplit, int64_t R, int64_t P, double* partial,
+                             hipStream_t st) {
+    dim3 g((unsigned)cdiv(R, SF_ROWS), (unsigned)cdiv(P, 32));
+    hipLaunchKernelGGL(k_sfsum_rows, g, dim3(256), 0, st, phi, ksplit, R, P, partial);
+    return hipGetLastError();
 }
 
 }  // namespace qrfs

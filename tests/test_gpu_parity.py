@@ -5,6 +5,7 @@ the oracle; per-element relative error is meaningless at zero crossings):
   FP64        1e-11
   FP32        1e-5   (max error) -- FP32 MFMA, FP32 transcendentals
   SPLIT_BF16  1e-3   (max error) -- bf16 hi+lo operands, FP32 accumulation
+  BF16X6      1e-5   (max error) -- bf16 hi+mid+lo operands: FP32-class
 Integer work (R2 sequence) is compared bit for bit.
 """
 import math
@@ -18,7 +19,8 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-11, 1: 1e-5, 2: 1e-3}
+TOL = {0: 1e-11, 1: 1e-5, 2: 1e-3, 3: 1e-5}
+PRECS = [0, 1, 2, 3]
 
 
 @pytest.fixture(scope="module")
@@ -125,7 +127,7 @@ def _freqs(ctx, q, n_sets, K, L0=25.0, ap=None, fmin=1e-3, fmax=1e2, index=0):
     return fx, fy, w
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", PRECS)
 @pytest.mark.parametrize("R,R_block", [(300, 300), (300, 97), (40, 1), (133, 64)])
 def test_synthesize_parity(q, ctx, precision, R, R_block):
     K, P = 301, 150
@@ -140,7 +142,7 @@ def test_synthesize_parity(q, ctx, precision, R, R_block):
     report(f"synth p{precision} R{R} Rb{R_block}", host(out), ref, TOL[precision])
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", PRECS)
 def test_synthesize_phase_workload(q, ctx, precision):
     """The 32x32-point, K = 1024, R = 128 phase workload, whole output."""
     cfg = workloads.phase_fp64()
@@ -155,7 +157,7 @@ def test_synthesize_phase_workload(q, ctx, precision):
         report(f"phase workload p{precision} Rb{R_block}", host(out), ref, TOL[precision])
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", PRECS)
 def test_synthesize_given_coefficients(q, ctx, precision):
     K, P, R, R_block = 70, 45, 90, 33
     n_sets = math.ceil(R / R_block)
@@ -169,7 +171,7 @@ def test_synthesize_given_coefficients(q, ctx, precision):
     report(f"given coef p{precision}", host(out), ref, TOL[precision])
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 3])
 def test_synthesize_eq3_mode(q, ctx, precision):
     K, P, R = 123, 37, 70
     fx, fy, w = _freqs(ctx, q, 1, K)
@@ -182,7 +184,7 @@ def test_synthesize_eq3_mode(q, ctx, precision):
     report(f"eq3 p{precision}", host(out), ref, TOL[precision])
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", PRECS)
 def test_synthesize_degenerate_sizes(q, ctx, precision):
     for K, P, R in ((1, 1, 1), (1, 33, 2), (17, 1, 65)):
         fx, fy, w = _freqs(ctx, q, R, K)
@@ -195,7 +197,7 @@ def test_synthesize_degenerate_sizes(q, ctx, precision):
 
 # -------------------------------------------------------------- piston ----
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", PRECS)
 def test_piston_parity(q, ctx, precision):
     K, R, R_block = 257, 200, 64
     n_sets = math.ceil(R / R_block)
@@ -213,7 +215,7 @@ def test_piston_parity(q, ctx, precision):
 
 # -------------------------------------------------- differential piston ----
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", PRECS)
 def test_diff_piston_parity(q, ctx, precision):
     cfg = workloads.diffpiston()
     K, R, R_block = 333, 150, 70
@@ -229,7 +231,7 @@ def test_diff_piston_parity(q, ctx, precision):
     report(f"diff piston p{precision}", host(out), ref, TOL[precision])
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", PRECS)
 @pytest.mark.parametrize("R,R_block", [(500, 500), (500, 64), (60, 1)])
 def test_diff_piston_structure_parity(q, ctx, precision, R, R_block):
     cfg = workloads.diffpiston()
@@ -243,7 +245,7 @@ def test_diff_piston_structure_parity(q, ctx, precision, R, R_block):
     fx, fy, area = oracle.sample_logpolar(n_sets, K, cfg["fmin"], cfg["fmax"], index=1234)
     w = oracle.weights(fx, fy, area, r0=0.1, L0=25.0, D=cfg["D"])
     rsf, rse = oracle.diff_piston_sf(fx, fy, w, cfg["bx"], cfg["by"], R, R_block, K=K, seed=9)
-    tol = {0: 1e-10, 1: 2e-5, 2: 2e-3}[precision]
+    tol = {0: 1e-10, 1: 2e-5, 2: 2e-3, 3: 2e-5}[precision]
     g, gs = host(sf), host(se)
     print(f"sf p{precision} R{R} Rb{R_block}: max rel {np.max(np.abs(g / rsf - 1)):.3e}")
     assert np.max(np.abs(g / rsf - 1)) < tol
@@ -325,7 +327,7 @@ def test_invalid_arguments_raise(q, ctx):
     assert e.value.status == q.ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", PRECS)
 def test_diff_piston_structure_sets_equals_end_to_end(q, ctx, precision):
     """The set-level entry gives bit-identical results to the end-to-end one
     when handed the same frequency sets."""
