@@ -253,6 +253,55 @@ QRFS_API qrfs_status qrfs_diff_piston_structure_sets(qrfs_context* ctx, int64_t 
                                                      double* sf, double* sf_stderr,
                                                      void* stream);
 
+/* ------------------------------------------------------ batched launches */
+/* Many uneven phase-field instances in one persistent launch (the phase of
+ * Eq. 3 at each instance's points, as qrfs_synthesize_phase computes it).
+ * Each instance brings its own PSD, sampler (the instance draws
+ * ceil(R/R_block) sets of K frequencies starting at sampler.index), points,
+ * realisations and output.  The batch owns the frequency buffers; executing
+ * it runs, on one stream: per instance the sampler and the weights, then one
+ * persistent kernel whose blocks pull (instance, set, row tile, column tile)
+ * work items, longest first, from a device counter.  Executions replay the
+ * same draws (sampler indices and rng counters are not advanced).
+ * Pointers inside an instance must stay valid until qrfs_batch_destroy. */
+typedef struct {
+    qrfs_psd psd;         /* phase PSD of the instance                  */
+    qrfs_sampler sampler; /* R2 placement; LEARNED is not accepted      */
+    int64_t K;            /* frequencies per set                        */
+    int64_t P;            /* points                                     */
+    const double* px;     /* device double[P]                           */
+    const double* py;     /* device double[P]                           */
+    int64_t R;            /* realisations                               */
+    int64_t R_block;      /* realisations per frequency set, in [1, R]  */
+    qrfs_rng rng;         /* coefficient stream (GAUSS_CS or EQ3)       */
+    float* phase;         /* device float[R][P] output                  */
+} qrfs_batch_instance;
+
+typedef struct qrfs_batch qrfs_batch;
+
+/* Builds the work list of n instances (host array, copied).  precision:
+ * QRFS_PREC_FP32, QRFS_PREC_SPLIT_BF16 or QRFS_PREC_BF16X6 (FP64 ->
+ * QRFS_ERR_UNSUPPORTED).  Allocates the batch's device buffers.
+ * Errors: n <= 0 or > 65535, any instance invalid as for
+ * qrfs_synthesize_phase / qrfs_sample_frequencies / qrfs_weights. */
+QRFS_API qrfs_status qrfs_batch_create(qrfs_context* ctx, int64_t n,
+                                       const qrfs_batch_instance* inst, int32_t precision,
+                                       qrfs_batch** out);
+/* Times every candidate launch shape (rows and columns per block, resident
+ * blocks per CU) on this batch and keeps the fastest; synchronises the
+ * stream.  best_ms (host, may be NULL) receives its time in ms. */
+QRFS_API qrfs_status qrfs_batch_autotune(qrfs_batch* b, void* stream, double* best_ms);
+/* Enqueues one execution on `stream`.  use_graph != 0: the first call
+ * captures the whole sequence in a HIP graph (re-captured after an autotune
+ * changes the shape), later calls replay it. */
+QRFS_API qrfs_status qrfs_batch_execute(qrfs_batch* b, int32_t use_graph, void* stream);
+/* Host outputs (each may be NULL): number of work items, chosen shape
+ * index, total terms R*K*P of one execution. */
+QRFS_API qrfs_status qrfs_batch_info(const qrfs_batch* b, int64_t* n_items, int32_t* shape,
+                                     double* terms);
+/* Synchronises the device and frees the batch.  NULL is accepted. */
+QRFS_API qrfs_status qrfs_batch_destroy(qrfs_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

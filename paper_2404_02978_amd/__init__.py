@@ -63,6 +63,12 @@ class Rng(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("counter", ctypes.c_uint64), ("mode", ctypes.c_int32)]
 
 
+class BatchInstance(ctypes.Structure):
+    _fields_ = [("psd", Psd), ("sampler", Sampler), ("K", ctypes.c_int64), ("P", ctypes.c_int64),
+                ("px", ctypes.c_void_p), ("py", ctypes.c_void_p), ("R", ctypes.c_int64),
+                ("R_block", ctypes.c_int64), ("rng", Rng), ("phase", ctypes.c_void_p)]
+
+
 def psd(r0, L0=None, model=None, c=0.0):
     if model is None:
         model = PSD_KOLMOGOROV if L0 is None else PSD_VON_KARMAN
@@ -114,6 +120,15 @@ def load_library():
                                            _P, _P, ctypes.POINTER(Sampler), _I64, _I64, _I64,
                                            ctypes.POINTER(Rng), _I32, _P, _P, _P]),
     }
+    sig.update({
+        "qrfs_batch_create": (S, [_P, _I64, ctypes.POINTER(BatchInstance), _I32,
+                                  ctypes.POINTER(_P)]),
+        "qrfs_batch_autotune": (S, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
+        "qrfs_batch_execute": (S, [_P, _I32, _P]),
+        "qrfs_batch_info": (S, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32),
+                                ctypes.POINTER(ctypes.c_double)]),
+        "qrfs_batch_destroy": (S, [_P]),
+    })
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype = res
@@ -278,3 +293,58 @@ class Context:
             R_block, ctypes.byref(rng), precision, _ptr(sf), _ptr(se if with_stderr else None),
             _stream()))
         return sf, se
+
+
+class Batch:
+    """Many uneven phase-field instances in one persistent launch.
+
+    instances: list of dicts with keys psd, sampler, K, px, py (float64 CUDA
+    tensors), R, R_block, rng; outputs are allocated here (float32 [R][P]).
+    """
+
+    def __init__(self, ctx, instances, precision=PREC_BF16X6):
+        lib = load_library()
+        self.ctx = ctx
+        self.outputs = []
+        self._keep = []
+        arr = (BatchInstance * len(instances))()
+        for i, d in enumerate(instances):
+            px, py = d["px"], d["py"]
+            P = px.numel()
+            out = torch.empty((d["R"], P), dtype=torch.float32, device=ctx.device)
+            self.outputs.append(out)
+            self._keep += [px, py]
+            arr[i] = BatchInstance(d["psd"], d["sampler"], d["K"], P, _dev_f64(px, "px"),
+                                   _dev_f64(py, "py", P), d["R"], d.get("R_block", d["R"]),
+                                   d.get("rng", Rng(0, 0, COEF_GAUSS_CS)), _ptr(out))
+        h = _P()
+        _check(lib.qrfs_batch_create(ctx.handle, len(instances), arr, precision, ctypes.byref(h)))
+        self._h = h
+
+    def autotune(self):
+        ms = ctypes.c_double(0.0)
+        _check(load_library().qrfs_batch_autotune(self._h, _stream(), ctypes.byref(ms)))
+        return ms.value
+
+    def execute(self, use_graph=False):
+        _check(load_library().qrfs_batch_execute(self._h, 1 if use_graph else 0, _stream()))
+        return self.outputs
+
+    def info(self):
+        n = _I64(0)
+        shape = _I32(0)
+        terms = ctypes.c_double(0.0)
+        _check(load_library().qrfs_batch_info(self._h, ctypes.byref(n), ctypes.byref(shape),
+                                              ctypes.byref(terms)))
+        return {"n_items": n.value, "shape": shape.value, "terms": terms.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().qrfs_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -221,6 +221,21 @@ qrfs_status sum_entry(qrfs_context* ctx, int basis, int64_t K, const double* fx,
 
 }  // namespace
 
+namespace qrfs {
+// shared with the batch layer
+qrfs_status api_fail(qrfs_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_detail = buf;
+    return s;
+}
+qrfs_status api_ok() { return ok(); }
+int api_context_device(const qrfs_context* ctx) { return ctx->device; }
+}  // namespace qrfs
+
 extern "C" {
 
 const char* qrfs_error_string(qrfs_status s) {

@@ -60,6 +60,28 @@ struct SfPlan {
 };
 SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P);
 
+// One work item of a persistent batch: instance, set, row tile, column tile.
+struct BatchItem {
+    int32_t inst;
+    int32_t set;
+    int32_t rt;
+    int32_t ct;
+};
+
+// Launch shape of the persistent batch kernel: rows per wave (32 MW),
+// columns per block (32 NB), resident blocks per CU of the grid.
+struct BatchShape {
+    int MW, NB, blocks_per_cu;
+};
+int batch_shape_count(int precision);
+BatchShape batch_shape(int precision, int id);
+
+// Resets the work counter and launches the persistent kernel (256 threads
+// per block, n_blocks blocks) over items[0 .. n_items).
+hipError_t launch_batch(int precision, BatchShape shape, const SumArgs* inst,
+                        const BatchItem* items, int n_items, unsigned* counter, int n_blocks,
+                        hipStream_t st);
+
 // squares of the K-range partial sums, summed per column over blocks of
 // rows: partial[ceil(R/256)][P][2]
 hipError_t launch_sfsum_rows(const float* phi, int ksplit, int64_t R, int64_t P, double* partial,

@@ -308,17 +308,36 @@ __device__ __forceinline__ void coef4_src(const SumArgs& a, int64_t row, bool ro
     }
 }
 
+// LDS of one block of the MFMA kernel
+template <int PREC, int NB>
+struct MfmaSmem {
+    static constexpr int NT = 32 * NB;
+    static constexpr int NPL = PREC == 2 ? 2 : 3;  // bf16 planes per operand (split modes)
+    static constexpr int NBF = PREC == 1 ? 2 * NT * STR_F32 : 4;
+    static constexpr int NBH = PREC >= 2 ? 2 * NT * STR_H : 8;
+    __attribute__((aligned(16))) float sBf[NBF];
+    __attribute__((aligned(16))) __bf16 sBp[NPL][NBH];
+    double sred[4][NT][2];
+    double spx[NT], spy[NT], sD[NT], sd[NT];
+};
+
+// One output tile: rows [row tile rt of set sl], columns [column tile ct],
+// frequency range ks.  Called once per block by k_sum_mfma and once per
+// work item by the persistent batch kernel; every thread of the block must
+// call it (it synchronises the block).
 template <int PREC, int BASIS, int EPI, int MW, int NB, int CSRC>
-__global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
-                                                  int64_t col_tiles) {
+__device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, int64_t sl,
+                                         int64_t rt, int64_t ct, int64_t ks,
+                                         MfmaSmem<PREC, NB>& sm) {
     constexpr int NT = 32 * NB;
-    constexpr int NPL = PREC == 2 ? 2 : 3;  // bf16 planes per operand (split modes)
-    constexpr int NBF = PREC == 1 ? 2 * NT * STR_F32 : 4;
-    constexpr int NBH = PREC >= 2 ? 2 * NT * STR_H : 8;
-    __shared__ __attribute__((aligned(16))) float sBf[NBF];
-    __shared__ __attribute__((aligned(16))) __bf16 sBp[NPL][NBH];
-    __shared__ double sred[4][NT][2];
-    __shared__ double spx[NT], spy[NT], sD[NT], sd[NT];
+    constexpr int NPL = MfmaSmem<PREC, NB>::NPL;
+    float* sBf = sm.sBf;
+    auto& sBp = sm.sBp;
+    auto& sred = sm.sred;
+    double* spx = sm.spx;
+    double* spy = sm.spy;
+    double* sD = sm.sD;
+    double* sd = sm.sd;
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -326,15 +345,6 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
     const int lr = lane & 31;
     const int lh = lane >> 5;
     const int64_t MT = 32 * MW * WV;
-
-    // tile: column tile fastest, then K split, row tile, set
-    int64_t bidx = blockIdx.x;
-    const int64_t ct = bidx % col_tiles;
-    bidx /= col_tiles;
-    const int64_t ks = bidx % a.ksplit;
-    bidx /= a.ksplit;
-    const int64_t rt = bidx % row_tiles;
-    const int64_t sl = bidx / row_tiles;
     const int64_t set = a.set0 + sl;
     const int64_t row_begin = set * a.R_block + rt * MT;
     const int64_t row_end = (set + 1) * a.R_block < a.R ? (set + 1) * a.R_block : a.R;
@@ -580,6 +590,58 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
     }
 }
 
+template <int PREC, int BASIS, int EPI, int MW, int NB, int CSRC>
+__global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
+                                                  int64_t col_tiles) {
+    __shared__ MfmaSmem<PREC, NB> sm;
+    // tile: column tile fastest, then K split, row tile, set
+    int64_t bidx = blockIdx.x;
+    const int64_t ct = bidx % col_tiles;
+    bidx /= col_tiles;
+    const int64_t ks = bidx % a.ksplit;
+    bidx /= a.ksplit;
+    const int64_t rt = bidx % row_tiles;
+    const int64_t sl = bidx / row_tiles;
+    sum_tile<PREC, BASIS, EPI, MW, NB, CSRC>(a, row_tiles, sl, rt, ct, ks, sm);
+}
+
+// ----------------------------------------------------- batch kernels ----
+// Persistent batch of uneven phase-field instances: a grid sized to the chip
+// pulls work items (instance, set, row tile, column tile) from a global
+// counter until the list is exhausted.  Items are ordered by decreasing
+// cost (longest first), so the tail of the launch is made of small items.
+// The counter is advanced with a vector atomic by one lane; every wave of
+// every block reaches the exit test on each iteration.
+template <int PREC, int MW, int NB>
+__global__ __launch_bounds__(256) void k_batch_persistent(const SumArgs* __restrict__ inst,
+                                                          const BatchItem* __restrict__ items,
+                                                          int n_items,
+                                                          unsigned* __restrict__ counter) {
+    __shared__ MfmaSmem<PREC, NB> sm;
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const BatchItem w = items[it];
+        const SumArgs a = inst[w.inst];
+        const int64_t row_tiles = (a.R_block + 32 * MW * (blockDim.x >> 6) - 1) /
+                                  (32 * MW * (blockDim.x >> 6));
+        if (a.mode == 0)
+            sum_tile<PREC, BASIS_PHASE, EPI_STORE, MW, NB, 0>(a, row_tiles, w.set, w.rt, w.ct, 0, sm);
+        else
+            sum_tile<PREC, BASIS_PHASE, EPI_STORE, MW, NB, 1>(a, row_tiles, w.set, w.rt, w.ct, 0, sm);
+        __syncthreads();
+    }
+}
+
+// Zeroes the work counter with a plain store (graph-capturable, no memset node).
+__global__ void k_reset_counter(unsigned* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
 // ----------------------------------------------------- split-K squares ----
 // Block (row block rb, column tile): 256 threads = 8 row groups x 32
 // columns.  Adds the K-range partial sums of each differential piston in a
@@ -799,6 +861,53 @@ hipError_t launch_sum(int precision, int basis, int epi, const SumArgs& a, hipSt
         return launch_be<BASIS_DIFF, EPI_STORE>(precision, a, st);
     }
     return launch_be<BASIS_DIFF, EPI_SFSUM>(precision, a, st);
+}
+
+// Batch launch shapes the autotuner chooses from: (MW, NB) per precision
+// and the number of resident blocks per CU of the persistent grid.
+static const BatchShape kShapesF32[] = {{1, 2, 2}, {1, 2, 3}, {1, 1, 4}, {1, 2, 4}};
+static const BatchShape kShapesSplit[] = {{2, 2, 1}, {2, 2, 2}, {1, 2, 2}, {1, 2, 3}};
+
+int batch_shape_count(int precision) { return precision == 1 ? 4 : 4; }
+
+BatchShape batch_shape(int precision, int id) {
+    return precision == 1 ? kShapesF32[id] : kShapesSplit[id];
+}
+
+template <int PREC, int MW, int NB>
+static hipError_t launch_batch_t(const SumArgs* inst, const BatchItem* items, int n_items,
+                                 unsigned* counter, int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_batch_persistent<PREC, MW, NB>), dim3((unsigned)n_blocks), dim3(256), 0,
+                       st, inst, items, n_items, counter);
+    return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_batch_p(int MW, int NB, const SumArgs* inst, const BatchItem* items,
+                                 int n_items, unsigned* counter, int n_blocks, hipStream_t st) {
+    if (MW == 2 && NB == 2) {
+        if constexpr (PREC != 1)
+            return launch_batch_t<PREC, 2, 2>(inst, items, n_items, counter, n_blocks, st);
+        return hipErrorInvalidValue;
+    }
+    if (MW == 1 && NB == 2)
+        return launch_batch_t<PREC, 1, 2>(inst, items, n_items, counter, n_blocks, st);
+    if (MW == 1 && NB == 1)
+        return launch_batch_t<PREC, 1, 1>(inst, items, n_items, counter, n_blocks, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch(int precision, BatchShape shape, const SumArgs* inst,
+                        const BatchItem* items, int n_items, unsigned* counter, int n_blocks,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (precision == 1)
+        return launch_batch_p<1>(shape.MW, shape.NB, inst, items, n_items, counter, n_blocks, st);
+    if (precision == 2)
+        return launch_batch_p<2>(shape.MW, shape.NB, inst, items, n_items, counter, n_blocks, st);
+    return launch_batch_p<3>(shape.MW, shape.NB, inst, items, n_items, counter, n_blocks, st);
 }
 
 hipError_t launch_sfsum_rows(const float* phi, int ksplit, int64_t R, int64_t P, double* partial,

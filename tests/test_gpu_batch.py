@@ -1,0 +1,115 @@
+"""Batched persistent launches of uneven phase-field instances against the
+FP64 oracle: eager execution, graph replays (eager work between replays,
+every replay checked), and after the autotuner picked a shape."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {1: 1e-5, 2: 1e-3, 3: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2404_02978_amd as q
+    q.load_library()
+    return q
+
+
+@pytest.fixture(scope="module")
+def ctx(q):
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def instances(q, R_block_div=1):
+    out, refs = [], []
+    for i, d in enumerate(workloads.small_batched()):
+        R = d["R"]
+        R_block = max(1, R // R_block_div)
+        index = 1000 * i
+        s = q.logpolar_sampler(workloads.FMIN, workloads.FMAX, index=index)
+        out.append(dict(psd=q.psd(d["r0"], d["L0"]), sampler=s, K=d["K"], px=dev(d["px"]),
+                        py=dev(d["py"]), R=R, R_block=R_block,
+                        rng=q.Rng(d["seed"], d["counter"], q.COEF_GAUSS_CS)))
+        n_sets = math.ceil(R / R_block)
+        fx, fy, area = oracle.sample_logpolar(n_sets, d["K"], workloads.FMIN, workloads.FMAX,
+                                              index=index)
+        w = oracle.weights(fx, fy, area, r0=d["r0"], L0=d["L0"])
+        refs.append(oracle.synthesize(fx, fy, w, d["px"], d["py"], R, R_block, K=d["K"],
+                                      seed=d["seed"], counter=d["counter"]))
+    return out, refs
+
+
+def check(outs, refs, tol, tag):
+    torch.cuda.synchronize()
+    for i, (o, r) in enumerate(zip(outs, refs)):
+        g = o.double().cpu().numpy()
+        e = np.max(np.abs(g - r)) / math.sqrt(np.mean(r * r))
+        print(f"{tag} instance {i}: eps_max {e:.3e}")
+        assert e <= tol, (tag, i, e)
+
+
+@pytest.mark.parametrize("precision", [1, 2, 3])
+@pytest.mark.parametrize("R_block_div", [1, 3])
+def test_batch_matches_oracle(q, ctx, precision, R_block_div):
+    inst, refs = instances(q, R_block_div)
+    b = q.Batch(ctx, inst, precision=precision)
+    info = b.info()
+    assert info["n_items"] > 0
+    check(b.execute(), refs, TOL[precision], f"eager p{precision}")
+    b.close()
+
+
+def test_batch_graph_replays(q, ctx):
+    inst, refs = instances(q, 2)
+    b = q.Batch(ctx, inst, precision=3)
+    eager = [o.clone() for o in b.execute()]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in b.outputs:
+            o.fill_(float("nan"))
+        x = torch.randn(1 << 20, device="cuda")  # unrelated eager work between replays
+        y = (x * 2.0).sum()
+        b.execute(use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.isfinite(y)
+        for o, e in zip(b.outputs, eager):
+            assert torch.equal(o, e), rep
+    check(b.outputs, refs, TOL[3], "graph")
+    b.close()
+
+
+def test_batch_autotune(q, ctx):
+    inst, refs = instances(q, 1)
+    b = q.Batch(ctx, inst, precision=3)
+    ms = b.autotune()
+    assert ms > 0
+    shape = b.info()["shape"]
+    print("autotuned shape", shape, "ms", ms)
+    check(b.execute(use_graph=True), refs, TOL[3], "autotuned graph")
+    check(b.execute(), refs, TOL[3], "autotuned eager")
+    b.close()
+
+
+def test_batch_rejects_bad_instances(q, ctx):
+    inst, _ = instances(q, 1)
+    bad = dict(inst[0])
+    bad["R_block"] = bad["R"] + 1
+    with pytest.raises(q.QrfsError) as e:
+        q.Batch(ctx, [inst[1], bad], precision=1)
+    assert e.value.status == q.ERR_INVALID_ARG
+    with pytest.raises(q.QrfsError) as e:
+        q.Batch(ctx, inst[:2], precision=0)
+    assert e.value.status == q.ERR_UNSUPPORTED
