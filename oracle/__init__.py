@@ -54,6 +54,18 @@ def _load():
         "oracle_diff_piston_sf": (None, [_i64, _p, _p, _p, _i64, _p, _p, _i64, _i64, _u64,
                                          _u64, _i32, _p, _p]),
     }
+    sig.update({
+        "oracle_mlp_param_count": (_i64, [ctypes.c_int]),
+        "oracle_mlp_forward": (None, [_p, ctypes.c_int, _d, _d, _i64, _p, _p, _p]),
+        "oracle_mlp_loss_grad": (_d, [_p, ctypes.c_int, _d, _d, _i64, _i64, _p, _p, _p, _p,
+                                      ctypes.c_int, _p]),
+        "oracle_proposal_rows": (None, [_u64, _u64, _u64, _i64, _i64, _p, _d, _d, _d, _d, _p, _p,
+                                        _p]),
+        "oracle_proposal_table": (None, [_p, ctypes.c_int, _d, _d, ctypes.c_int, _d, _d, _i64, _p,
+                                         _p, _d, _p, _p, _p, _p]),
+        "oracle_sample_learned": (None, [_u64, _u64, _u64, _i64, _i64, _d, _d, ctypes.c_int, _p,
+                                         _p, _p, _p, _p, _p, _p]),
+    })
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype = res
@@ -186,3 +198,55 @@ def diff_piston_sf(fx, fy, w, bx, by, R, R_block, K=None, seed=0, counter=0,
     _load().oracle_diff_piston_sf(K, _ptr(fx), _ptr(fy), _ptr(w), bx.size, _ptr(bx), _ptr(by),
                                   R, R_block, seed, counter, mode, _ptr(sf), _ptr(se))
     return sf, se
+
+
+# ------------------------------------------------------ learned proposal
+def mlp_param_count(H=128):
+    return int(_load().oracle_mlp_param_count(H))
+
+
+def mlp_forward(prm, ell, ctx, lmin, Lw, H=128):
+    prm, ell = _f64(prm), _f64(ell)
+    ctx = _f64(np.broadcast_to(np.asarray(ctx, dtype=np.float64), (ell.size, 4)))
+    out = np.zeros((ell.size, 2))
+    _load().oracle_mlp_forward(_ptr(prm), H, lmin, Lw, ell.size, _ptr(ell), _ptr(ctx), _ptr(out))
+    return out
+
+
+def mlp_loss_grad(prm, ctx, ell, theta, h, lmin, Lw, G=64, H=128):
+    prm, ctx, ell, theta, h = map(_f64, (prm, ctx, ell, theta, h))
+    n_ctx = ctx.size // 4
+    m = ell.size // n_ctx
+    grad = np.zeros(prm.size)
+    loss = _load().oracle_mlp_loss_grad(_ptr(prm), H, lmin, Lw, n_ctx, m, _ptr(ctx), _ptr(ell),
+                                        _ptr(theta), _ptr(h), G, _ptr(grad))
+    return loss, grad
+
+
+def proposal_rows(ctx, m, r0, fmin, fmax, index=0, c=None, s0x=SEED_HALF, s0y=SEED_HALF):
+    ctx = _f64(ctx)
+    n = ctx.size // 4 * m
+    ell, theta, h = np.zeros(n), np.zeros(n), np.zeros(n)
+    c = psd_constant() if c is None else c
+    _load().oracle_proposal_rows(s0x, s0y, index, ctx.size // 4, m, _ptr(ctx), r0, c, fmin, fmax,
+                                 _ptr(ell), _ptr(theta), _ptr(h))
+    return ell, theta, h
+
+
+def proposal_table(prm, D, L0, bl, bth, fmin, fmax, n_cells=256, beta=0.1, H=128):
+    prm, bl, bth = _f64(prm), _f64(bl), _f64(bth)
+    p, al, ph, cdf = (np.zeros(n_cells) for _ in range(4))
+    _load().oracle_proposal_table(_ptr(prm), H, np.log(fmin), np.log(fmax / fmin), n_cells, D, L0,
+                                  bl.size, _ptr(bl), _ptr(bth), beta, _ptr(p), _ptr(al), _ptr(ph),
+                                  _ptr(cdf))
+    return p, al, ph, cdf
+
+
+def sample_learned(table, n_sets, K, fmin, fmax, index=0, s0x=SEED_HALF, s0y=SEED_HALF):
+    p, al, ph, cdf = map(_f64, table)
+    n = n_sets * K
+    fx, fy, area = np.zeros(n), np.zeros(n), np.zeros(n)
+    _load().oracle_sample_learned(s0x, s0y, index, n_sets, K, np.log(fmin), np.log(fmax / fmin),
+                                  p.size, _ptr(p), _ptr(al), _ptr(ph), _ptr(cdf), _ptr(fx),
+                                  _ptr(fy), _ptr(area))
+    return fx, fy, area

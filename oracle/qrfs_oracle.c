@@ -370,3 +370,292 @@ ORACLE_API void oracle_diff_piston_sf(int64_t K, const double* fx, const double*
     free(px);
     free(py);
 }
+
+/* ------------------------------------------------------------------ */
+/* Learned proposal density (the paper suggests systematising the      */
+/* sampling with a mapping that knows the PSD, Sec. 5; the model below */
+/* is this project's definition of such a mapping)                     */
+/* ------------------------------------------------------------------ */
+/* Network: x (5 features) -> h1 = tanh(W1 x + b1) (H) -> h2 = tanh(W2 h1 +
+ * b2) (H) -> o = W3 h2 + b3 (2).  Flat parameter layout: W1[H][5], b1[H],
+ * W2[H][H], b2[H], W3[2][H], b3[2].  Features of (ell = ln|f|, context
+ * D, L0, |B|, theta_B) over the band [lmin, lmin + Lw]:
+ *   (2 (ell - lmin)/Lw - 1, 2 theta_B/pi - 1, ln(D)/4, ln(L0)/4 - 1, ln|B|/4 - 1/2).
+ * Density over (ell, theta): q = p(ell) (1 + alpha cos 2(theta - theta_B)) / (2 pi),
+ * p proportional to exp(o0), alpha = 0.9 tanh(o1). */
+
+static void mlp_features(double ell, double lmin, double Lw, const double ctx[4], double x[5]) {
+    x[0] = 2.0 * (ell - lmin) / Lw - 1.0;
+    x[1] = 2.0 * ctx[3] / M_PI - 1.0;
+    x[2] = log(ctx[0]) / 4.0;
+    x[3] = log(ctx[1]) / 4.0 - 1.0;
+    x[4] = log(ctx[2]) / 4.0 - 0.5;
+}
+
+/* forward of one row; h1, h2 (length H) receive the activations */
+static void mlp_row(const double* prm, int H, const double x[5], double* h1, double* h2,
+                    double o[2]) {
+    const double* W1 = prm;
+    const double* b1 = W1 + 5 * H;
+    const double* W2 = b1 + H;
+    const double* b2 = W2 + H * H;
+    const double* W3 = b2 + H;
+    const double* b3 = W3 + 2 * H;
+    for (int i = 0; i < H; ++i) {
+        double s = b1[i];
+        for (int j = 0; j < 5; ++j) s += W1[i * 5 + j] * x[j];
+        h1[i] = tanh(s);
+    }
+    for (int i = 0; i < H; ++i) {
+        double s = b2[i];
+        for (int j = 0; j < H; ++j) s += W2[i * H + j] * h1[j];
+        h2[i] = tanh(s);
+    }
+    for (int k = 0; k < 2; ++k) {
+        double s = b3[k];
+        for (int j = 0; j < H; ++j) s += W3[k * H + j] * h2[j];
+        o[k] = s;
+    }
+}
+
+ORACLE_API int64_t oracle_mlp_param_count(int H) { return 5 * H + H + H * H + H + 2 * H + 2; }
+
+/* o[N][2] for rows (ell[i], ctx[i][4]) */
+ORACLE_API void oracle_mlp_forward(const double* prm, int H, double lmin, double Lw, int64_t N,
+                                   const double* ell, const double* ctx, double* out) {
+#pragma omp parallel
+    {
+        double* h1 = (double*)malloc(sizeof(double) * (size_t)H);
+        double* h2 = (double*)malloc(sizeof(double) * (size_t)H);
+#pragma omp for
+        for (int64_t i = 0; i < N; ++i) {
+            double x[5];
+            mlp_features(ell[i], lmin, Lw, ctx + 4 * i, x);
+            mlp_row(prm, H, x, h1, h2, out + 2 * i);
+        }
+        free(h1);
+        free(h2);
+    }
+}
+
+/* backward of one row: adds dL/dprm given dL/do (do[2]) */
+static void mlp_row_backward(const double* prm, int H, const double x[5], const double* h1,
+                             const double* h2, const double dout[2], double* grad) {
+    const double* W2 = prm + 5 * H + H;
+    const double* W3 = W2 + H * H + H;
+    double* gW1 = grad;
+    double* gb1 = gW1 + 5 * H;
+    double* gW2 = gb1 + H;
+    double* gb2 = gW2 + H * H;
+    double* gW3 = gb2 + H;
+    double* gb3 = gW3 + 2 * H;
+    double* d2 = (double*)malloc(sizeof(double) * (size_t)H);
+    double* d1 = (double*)malloc(sizeof(double) * (size_t)H);
+    for (int k = 0; k < 2; ++k) {
+        gb3[k] += dout[k];
+        for (int j = 0; j < H; ++j) gW3[k * H + j] += dout[k] * h2[j];
+    }
+    for (int j = 0; j < H; ++j) {
+        double s = dout[0] * W3[j] + dout[1] * W3[H + j];
+        d2[j] = s * (1.0 - h2[j] * h2[j]);
+    }
+    for (int i = 0; i < H; ++i) {
+        gb2[i] += d2[i];
+        for (int j = 0; j < H; ++j) gW2[i * H + j] += d2[i] * h1[j];
+    }
+    for (int j = 0; j < H; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < H; ++i) s += W2[i * H + j] * d2[i];
+        d1[j] = s * (1.0 - h1[j] * h1[j]);
+    }
+    for (int i = 0; i < H; ++i) {
+        gb1[i] += d1[i];
+        for (int j = 0; j < 5; ++j) gW1[i * 5 + j] += d1[i] * x[j];
+    }
+    free(d1);
+    free(d2);
+}
+
+/* Loss and gradient of one mini-batch.  Contexts c < n_ctx (ctx[c][4]);
+ * each owns m sample rows (ell, theta, h) at rows c*m .. c*m+m-1 and the
+ * G-point midpoint grid of [lmin, lmin+Lw] that normalises p:
+ *   logZ_c = log( sum_j exp(o0(grid_j, c)) Lw/G )
+ *   L = -(1/H) sum_i h_i [ o0_i - logZ_c(i) + log(1 + alpha_i cos 2(theta_i - theta_B)) ]
+ * with H = sum_i h_i, alpha = 0.9 tanh(o1).  grad receives dL/dprm. */
+ORACLE_API double oracle_mlp_loss_grad(const double* prm, int Hd, double lmin, double Lw,
+                                       int64_t n_ctx, int64_t m, const double* ctx,
+                                       const double* ell, const double* theta, const double* h,
+                                       int G, double* grad) {
+    int64_t np = oracle_mlp_param_count(Hd);
+    for (int64_t i = 0; i < np; ++i) grad[i] = 0.0;
+    double* h1 = (double*)malloc(sizeof(double) * (size_t)Hd);
+    double* h2 = (double*)malloc(sizeof(double) * (size_t)Hd);
+    double* og = (double*)malloc(sizeof(double) * (size_t)G);
+    double Htot = 0.0;
+    for (int64_t i = 0; i < n_ctx * m; ++i) Htot += h[i];
+    double loss = 0.0;
+    for (int64_t c = 0; c < n_ctx; ++c) {
+        const double* cc = ctx + 4 * c;
+        /* grid forward and log-normaliser */
+        double mx = -1e300;
+        for (int j = 0; j < G; ++j) {
+            double x[5], o[2];
+            mlp_features(lmin + (j + 0.5) * Lw / G, lmin, Lw, cc, x);
+            mlp_row(prm, Hd, x, h1, h2, o);
+            og[j] = o[0];
+            if (o[0] > mx) mx = o[0];
+        }
+        double se = 0.0;
+        for (int j = 0; j < G; ++j) se += exp(og[j] - mx);
+        double logZ = mx + log(se * Lw / G);
+        double Hc = 0.0;
+        /* sample rows */
+        for (int64_t r = 0; r < m; ++r) {
+            int64_t i = c * m + r;
+            double x[5], o[2];
+            mlp_features(ell[i], lmin, Lw, cc, x);
+            mlp_row(prm, Hd, x, h1, h2, o);
+            double ta = tanh(o[1]);
+            double alpha = 0.9 * ta;
+            double C = cos(2.0 * (theta[i] - cc[3]));
+            double wi = h[i] / Htot;
+            loss -= wi * (o[0] - logZ + log(1.0 + alpha * C));
+            double dout[2] = {-wi, -wi * C / (1.0 + alpha * C) * 0.9 * (1.0 - ta * ta)};
+            mlp_row_backward(prm, Hd, x, h1, h2, dout, grad);
+            Hc += h[i];
+        }
+        /* grid rows: d logZ / d o0_j = softmax_j */
+        for (int j = 0; j < G; ++j) {
+            double x[5], o[2];
+            mlp_features(lmin + (j + 0.5) * Lw / G, lmin, Lw, cc, x);
+            mlp_row(prm, Hd, x, h1, h2, o);
+            double dout[2] = {(Hc / Htot) * exp(og[j] - mx) / se, 0.0};
+            mlp_row_backward(prm, Hd, x, h1, h2, dout, grad);
+        }
+    }
+    free(og);
+    free(h1);
+    free(h2);
+    return loss;
+}
+
+/* Training rows from the plain log-polar sampler: row i of context c uses
+ * R2 point index+1+c*m+r; h = f^2 W(f) F_D(f)^2 2 (1 - cos 2 pi f |B| cos(theta - theta_B)),
+ * the variance contribution per unit (ln f, theta) of the differential
+ * piston over B (Eq. 7 and the structure function of Sec. 4.4). */
+ORACLE_API void oracle_proposal_rows(uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n_ctx,
+                                     int64_t m, const double* ctx, double r0, double c_psd,
+                                     double fmin, double fmax, double* ell, double* theta,
+                                     double* h) {
+    int64_t n = n_ctx * m;
+    double* ux = (double*)malloc(sizeof(double) * (size_t)n);
+    double* uy = (double*)malloc(sizeof(double) * (size_t)n);
+    oracle_r2_points(s0x, s0y, index, n, ux, uy);
+    double lmin = log(fmin), Lw = log(fmax / fmin);
+    for (int64_t i = 0; i < n; ++i) {
+        const double* cc = ctx + 4 * (i / m);
+        double l = lmin + Lw * ux[i];
+        double th = 2.0 * M_PI * uy[i];
+        double f = exp(l);
+        double W = oracle_psd(1, c_psd, r0, cc[1], f);
+        double F = oracle_aperture_filter(cc[0], 0.0, f);
+        double proj = f * cc[2] * cos(th - cc[3]);
+        ell[i] = l;
+        theta[i] = th;
+        h[i] = f * f * W * F * F * 2.0 * (1.0 - cos(2.0 * M_PI * proj));
+    }
+    free(ux);
+    free(uy);
+}
+
+/* Sampling table of the proposal for aperture D, outer scale L0 and nB
+ * baselines (length bl[b], direction bth[b]): on n_cells equal cells of
+ * [lmin, lmin+Lw] (midpoints ell_j), per baseline p_b(j) = exp(o0)/Z_b with
+ * Z_b = sum_j exp(o0) dl, alpha_b(j) = 0.9 tanh(o1); the mixture over
+ * baselines has angular part sum_b p_b alpha_b cos 2(theta - theta_b) / nB
+ * = pbar (abar cos 2(theta - phi)); the defensive mixture adds beta of the
+ * plain density 1/Lw:  p = (1-beta) pbar + beta/Lw,
+ * alpha = (1-beta) pbar abar / p.  cdf[j] = sum_{i<j} p_i dl / sum_i p_i dl. */
+ORACLE_API void oracle_proposal_table(const double* prm, int H, double lmin, double Lw,
+                                      int n_cells, double D, double L0, int64_t nB,
+                                      const double* bl, const double* bth, double beta,
+                                      double* p, double* alpha, double* phi, double* cdf) {
+    double dl = Lw / n_cells;
+    double* pb = (double*)calloc((size_t)n_cells, sizeof(double));
+    double* A = (double*)calloc((size_t)n_cells, sizeof(double));
+    double* B = (double*)calloc((size_t)n_cells, sizeof(double));
+    double* o0 = (double*)malloc(sizeof(double) * (size_t)n_cells);
+    double* o1 = (double*)malloc(sizeof(double) * (size_t)n_cells);
+    double* h1 = (double*)malloc(sizeof(double) * (size_t)H);
+    double* h2 = (double*)malloc(sizeof(double) * (size_t)H);
+    for (int64_t b = 0; b < nB; ++b) {
+        double cc[4] = {D, L0, bl[b], bth[b]};
+        double mx = -1e300;
+        for (int j = 0; j < n_cells; ++j) {
+            double x[5], o[2];
+            mlp_features(lmin + (j + 0.5) * dl, lmin, Lw, cc, x);
+            mlp_row(prm, H, x, h1, h2, o);
+            o0[j] = o[0];
+            o1[j] = o[1];
+            if (o[0] > mx) mx = o[0];
+        }
+        double Z = 0.0;
+        for (int j = 0; j < n_cells; ++j) Z += exp(o0[j] - mx) * dl;
+        for (int j = 0; j < n_cells; ++j) {
+            double pj = exp(o0[j] - mx) / Z;
+            double al = 0.9 * tanh(o1[j]);
+            pb[j] += pj / (double)nB;
+            A[j] += pj * al * cos(2.0 * bth[b]) / (double)nB;
+            B[j] += pj * al * sin(2.0 * bth[b]) / (double)nB;
+        }
+    }
+    double tot = 0.0;
+    for (int j = 0; j < n_cells; ++j) {
+        double amp = sqrt(A[j] * A[j] + B[j] * B[j]);
+        p[j] = (1.0 - beta) * pb[j] + beta / Lw;
+        alpha[j] = (1.0 - beta) * amp / p[j];
+        phi[j] = 0.5 * atan2(B[j], A[j]);
+        tot += p[j] * dl;
+    }
+    double run = 0.0;
+    for (int j = 0; j < n_cells; ++j) {
+        p[j] /= tot;
+        cdf[j] = run;
+        run += p[j] * dl;
+    }
+    free(pb); free(A); free(B); free(o0); free(o1); free(h1); free(h2);
+}
+
+/* Learned frequency sampler: R2 point (u1, u2) -> cell j with
+ * cdf[j] <= u1 < cdf[j+1]; ell = lmin + j dl + (u1 - cdf[j]) / p[j]; the
+ * angle solves t + (alpha/2) sin 2t = 2 pi u2 (12 Newton steps from
+ * t = 2 pi u2), theta = t + phi[j]; area = f^2 / (K q) with
+ * q = p[j] (1 + alpha cos 2t) / (2 pi), the inverse density of the draw. */
+ORACLE_API void oracle_sample_learned(uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n_sets,
+                                      int64_t K, double lmin, double Lw, int n_cells,
+                                      const double* p, const double* alpha, const double* phi,
+                                      const double* cdf, double* fx, double* fy, double* area) {
+    int64_t n = n_sets * K;
+    double* ux = (double*)malloc(sizeof(double) * (size_t)n);
+    double* uy = (double*)malloc(sizeof(double) * (size_t)n);
+    oracle_r2_points(s0x, s0y, index, n, ux, uy);
+    double dl = Lw / n_cells;
+    for (int64_t i = 0; i < n; ++i) {
+        int j = n_cells - 1;
+        for (int c = 1; c < n_cells; ++c)
+            if (cdf[c] > ux[i]) { j = c - 1; break; }
+        double ell = lmin + j * dl + (ux[i] - cdf[j]) / p[j];
+        double target = 2.0 * M_PI * uy[i];
+        double t = target;
+        for (int it = 0; it < 12; ++it)
+            t -= (t + 0.5 * alpha[j] * sin(2.0 * t) - target) / (1.0 + alpha[j] * cos(2.0 * t));
+        double th = t + phi[j];
+        double f = exp(ell);
+        double q = p[j] * (1.0 + alpha[j] * cos(2.0 * t)) / (2.0 * M_PI);
+        fx[i] = f * cos(th);
+        fy[i] = f * sin(th);
+        area[i] = f * f / ((double)K * q);
+    }
+    free(ux);
+    free(uy);
+}

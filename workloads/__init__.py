@@ -91,3 +91,36 @@ def small_batched(n_inst=6, seed=1, R=40):
         inst.append(dict(D=D, n=n, K=K, L0=L0, r0=0.1, px=px, py=py, R=R - 7 * (i % 3),
                          seed=seed, counter=1000 * i))
     return inst
+
+
+def mlp_init(seed=0, H=128, scale=1.0):
+    """Seeded initial parameters of the 5 -> H -> H -> 2 proposal network
+    (flat layout W1[H][5], b1[H], W2[H][H], b2[H], W3[2][H], b3[2]):
+    uniform(-s, s) with s = scale / sqrt(fan_in), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((5, H), (H, H), (H, 2)):
+        s = scale / np.sqrt(fan_in)
+        parts.append(rng.uniform(-s, s, fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts)
+
+
+def proposal_contexts(n_ctx=512, seed=0):
+    """Training contexts (D, L0, |B|, theta_B): half the apertures at
+    D = 1.8 m, the rest log-uniform in [0.5, 10] m; L0 log-uniform in
+    [10, 100] m; |B| log-uniform in [1, 130] m; theta_B uniform in [0, pi)."""
+    rng = np.random.default_rng(seed)
+    D = np.where(np.arange(n_ctx) % 2 == 0, 1.8, np.exp(rng.uniform(np.log(0.5), np.log(10.0), n_ctx)))
+    L0 = np.exp(rng.uniform(np.log(10.0), np.log(100.0), n_ctx))
+    B = np.exp(rng.uniform(0.0, np.log(130.0), n_ctx))
+    th = rng.uniform(0.0, np.pi, n_ctx)
+    return np.stack([D, L0, B, th], axis=1)
+
+
+def learned(L0=25.0, R=100000):
+    """Differential piston with the learned proposal: D = 1.8 m, 32 x-baselines
+    1-130 m; learned K = 4096 vs plain K = 65536."""
+    bx, by = baselines()
+    return dict(name="learned", model=1, r0=0.10, L0=L0, fmin=FMIN, fmax=FMAX, K_learned=4096,
+                K_plain=65536, D=1.8, d=0.0, bx=bx, by=by, R=R, seed=0)
