@@ -115,7 +115,12 @@ typedef struct {
  *       N df = 2 max|f|, as the worked example of Sec. 4.4 fixes.
  *   R2_LOGPOLAR: |f| = fmin (fmax/fmin)^(u_x), angle = 2 pi u_y,
  *       cell area = 2 pi ln(fmax/fmin) |f|^2 / K.
- *   LEARNED: reserved (QRFS_ERR_UNSUPPORTED).
+ *   LEARNED: the points are drawn from the sampling table of `proposal`
+ *       (built by qrfs_proposal_tabulate): u_x through the inverse CDF of
+ *       its piecewise-constant density in ln|f| over [fmin, fmax] of the
+ *       proposal, u_y through the inverse CDF of its angular factor, and
+ *       each point gets the area f^2 / (K q), q the density of the draw, so
+ *       the weighted sums stay unbiased.
  * seed_x, seed_y: S0 in 0.64 fixed point (2^63 = 1/2, Sec. 3.2's (0.5, 0.5)).
  * index (IN/OUT): position in the sequence; every call advances it by the
  * number of points drawn, so consecutive calls continue the sequence. */
@@ -131,6 +136,7 @@ typedef struct {
     uint64_t seed_x;
     uint64_t seed_y;
     uint64_t index;
+    const struct qrfs_proposal* proposal; /* LEARNED only, else ignored */
 } qrfs_sampler;
 
 #define QRFS_COEF_GAUSS_CS 0
@@ -169,7 +175,8 @@ typedef struct {
  * cell area each point stands for to area (m^-2), all double[n_sets*K].
  * Cell areas are per set of K points.  s->index += n_sets*K on success.
  * Errors: K, n_sets <= 0; NULL pointers; Cartesian N <= 0 or df <= 0;
- * log-polar fmin <= 0 or fmax <= fmin; LEARNED -> QRFS_ERR_UNSUPPORTED. */
+ * log-polar fmin <= 0 or fmax <= fmin; LEARNED without a proposal or
+ * before its table was built. */
 QRFS_API qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s, int64_t n_sets,
                                     int64_t K, double* fx, double* fy, double* area,
                                     void* stream);
@@ -252,6 +259,86 @@ QRFS_API qrfs_status qrfs_diff_piston_structure_sets(qrfs_context* ctx, int64_t 
                                                      const qrfs_rng* rng, int32_t precision,
                                                      double* sf, double* sf_stderr,
                                                      void* stream);
+
+/* ------------------------------------------------------ learned proposal */
+/* A proposal density for the frequency sampler, learned from the variance
+ * contributions the plain method generates (the paper leaves the choice of
+ * the sampling to the user and suggests a PSD-aware mapping, Sec. 5):
+ *   q(ell, theta) = p(ell) (1 + alpha(ell) cos 2(theta - theta_B)) / (2 pi),
+ * ell = ln|f| in [ln fmin, ln fmax], p proportional to exp(o0),
+ * alpha = 0.9 tanh(o1), o = network(2 (ell - ln fmin)/Lw - 1,
+ * 2 theta_B/pi - 1, ln D / 4, ln L0 / 4 - 1, ln|B| / 4 - 1/2),
+ * Lw = ln(fmax/fmin), network 5 -> 128 (tanh) -> 128 (tanh) -> 2 with flat
+ * FP32 parameters W1[128][5], b1[128], W2[128][128], b2[128], W3[2][128],
+ * b3[2] (QRFS_PROPOSAL_NPARAM floats).  Training minimises the
+ * cross-entropy -sum h log q / sum h toward the contributions h of plain
+ * samples, with p normalised on a G-point midpoint grid; Adam (Kingma & Ba).
+ * The sampling table is piecewise constant on n_cells cells: the mixture of
+ * the per-baseline densities of a target geometry plus a defensive share
+ * beta of the plain density, so q > 0 everywhere. */
+#define QRFS_PROPOSAL_NPARAM 17538
+#define QRFS_PROPOSAL_MAX_CELLS 1024
+typedef struct qrfs_proposal qrfs_proposal;
+
+/* Creates a proposal over [fmin, fmax] with the given initial parameters
+ * (device float[QRFS_PROPOSAL_NPARAM], copied); Adam moments start at 0. */
+QRFS_API qrfs_status qrfs_proposal_create(qrfs_context* ctx, double fmin, double fmax,
+                                          const float* init_params, qrfs_proposal** out);
+QRFS_API qrfs_status qrfs_proposal_destroy(qrfs_proposal* p);
+/* Device-to-device copies of the parameters (float[QRFS_PROPOSAL_NPARAM]). */
+QRFS_API qrfs_status qrfs_proposal_get_params(const qrfs_proposal* p, float* dst, void* stream);
+QRFS_API qrfs_status qrfs_proposal_set_params(qrfs_proposal* p, const float* src, void* stream);
+/* Network outputs out[n][2] (o0, o1) for rows ell[n] with contexts
+ * ctx4[n][4] = (D, L0, |B|, theta_B); all device. */
+QRFS_API qrfs_status qrfs_proposal_forward(qrfs_proposal* p, int64_t n, const double* ell,
+                                           const double* ctx4, float* out, void* stream);
+/* Training rows from the plain log-polar sampler `plain` (advanced by
+ * n_ctx*m): context c (ctx4[c], device [n_ctx][4]) owns rows c*m .. c*m+m-1
+ * with ell, theta and the contribution
+ * h = f^2 W(f) F_D(f)^2 2 (1 - cos(2 pi f |B| cos(theta - theta_B)))
+ * of a von Karman PSD with Fried parameter r0 (c_psd <= 0: exact constant)
+ * and outer scale L0 of the context.  Outputs device double[n_ctx*m]. */
+QRFS_API qrfs_status qrfs_proposal_rows(qrfs_proposal* p, qrfs_sampler* plain, int64_t n_ctx,
+                                        int64_t m, const double* ctx4, double r0, double c_psd,
+                                        double* ell, double* theta, double* h, void* stream);
+/* Loss and its gradient for all n_ctx contexts of a training set (the
+ * training step's computation, exposed for checking): grad device
+ * float[QRFS_PROPOSAL_NPARAM], loss device double[1].  G: normaliser grid
+ * points (1..4096).  n_ctx <= 1024. */
+QRFS_API qrfs_status qrfs_proposal_loss_grad(qrfs_proposal* p, int64_t n_ctx, int64_t m,
+                                             const double* ctx4, const double* ell,
+                                             const double* theta, const double* h, int32_t G,
+                                             float* grad, double* loss, void* stream);
+/* `steps` Adam steps (learning rate lr) on mini-batches of ctx_per_step
+ * contexts (<= 1024) taken in an order reshuffled every epoch from
+ * shuffle_seed; loss_log: device double[steps] or NULL. */
+QRFS_API qrfs_status qrfs_proposal_train(qrfs_proposal* p, int64_t n_ctx, int64_t m,
+                                         const double* ctx4, const double* ell,
+                                         const double* theta, const double* h,
+                                         int64_t ctx_per_step, int64_t steps, int32_t G,
+                                         double lr, uint64_t shuffle_seed, double* loss_log,
+                                         void* stream);
+/* Builds the sampling table for aperture D, outer scale L0 and nB
+ * baselines of length blen[b] and direction bth[b] (host arrays), with
+ * n_cells (1..QRFS_PROPOSAL_MAX_CELLS) cells and defensive share beta in
+ * (0, 1]. */
+QRFS_API qrfs_status qrfs_proposal_tabulate(qrfs_proposal* p, double D, double L0, int64_t nB,
+                                            const double* blen, const double* bth,
+                                            int32_t n_cells, double beta, void* stream);
+/* Table access (device double[n_cells] each): density p of ln|f| per cell,
+ * alpha, phi (angular factor 1 + alpha cos 2(theta - phi)), cdf at the
+ * cell's left edge.  set_table replaces the table (cdf[0] = 0, increasing,
+ * p > 0, |alpha| < 1 are the caller's responsibility). */
+QRFS_API qrfs_status qrfs_proposal_get_table(const qrfs_proposal* p, int32_t* n_cells,
+                                             double* tp, double* talpha, double* tphi,
+                                             double* tcdf, void* stream);
+QRFS_API qrfs_status qrfs_proposal_set_table(qrfs_proposal* p, int32_t n_cells, const double* tp,
+                                             const double* talpha, const double* tphi,
+                                             const double* tcdf, void* stream);
+/* Parameters to / from a file: 8-byte magic "QRFSPRP1", fmin, fmax (double),
+ * QRFS_PROPOSAL_NPARAM floats (little-endian).  Synchronises the device. */
+QRFS_API qrfs_status qrfs_proposal_save(const qrfs_proposal* p, const char* path);
+QRFS_API qrfs_status qrfs_proposal_load(qrfs_proposal* p, const char* path);
 
 /* ------------------------------------------------------ batched launches */
 /* Many uneven phase-field instances in one persistent launch (the phase of

@@ -56,7 +56,7 @@ class Sampler(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("N", ctypes.c_int32), ("df", ctypes.c_double),
                 ("fmin", ctypes.c_double), ("fmax", ctypes.c_double),
                 ("seed_x", ctypes.c_uint64), ("seed_y", ctypes.c_uint64),
-                ("index", ctypes.c_uint64)]
+                ("index", ctypes.c_uint64), ("proposal", ctypes.c_void_p)]
 
 
 class Rng(ctypes.Structure):
@@ -76,11 +76,20 @@ def psd(r0, L0=None, model=None, c=0.0):
 
 
 def logpolar_sampler(fmin, fmax, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
-    return Sampler(SAMPLER_R2_LOGPOLAR, 0, 0.0, fmin, fmax, seed_x, seed_y, index)
+    return Sampler(SAMPLER_R2_LOGPOLAR, 0, 0.0, fmin, fmax, seed_x, seed_y, index, None)
 
 
 def cartesian_sampler(N, df, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
-    return Sampler(SAMPLER_R2_CARTESIAN, N, df, 0.0, 0.0, seed_x, seed_y, index)
+    return Sampler(SAMPLER_R2_CARTESIAN, N, df, 0.0, 0.0, seed_x, seed_y, index, None)
+
+
+def learned_sampler(proposal, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
+    """R2 points warped through the sampling table of `proposal`."""
+    return Sampler(SAMPLER_LEARNED, 0, 0.0, proposal.fmin, proposal.fmax, seed_x, seed_y, index,
+                   proposal.handle.value)
+
+
+PROPOSAL_NPARAM = 17538
 
 
 _lib = None
@@ -120,6 +129,25 @@ def load_library():
                                            _P, _P, ctypes.POINTER(Sampler), _I64, _I64, _I64,
                                            ctypes.POINTER(Rng), _I32, _P, _P, _P]),
     }
+    _D = ctypes.c_double
+    sig.update({
+        "qrfs_proposal_create": (S, [_P, _D, _D, _P, ctypes.POINTER(_P)]),
+        "qrfs_proposal_destroy": (S, [_P]),
+        "qrfs_proposal_get_params": (S, [_P, _P, _P]),
+        "qrfs_proposal_set_params": (S, [_P, _P, _P]),
+        "qrfs_proposal_forward": (S, [_P, _I64, _P, _P, _P, _P]),
+        "qrfs_proposal_rows": (S, [_P, ctypes.POINTER(Sampler), _I64, _I64, _P, _D, _D, _P, _P, _P,
+                                   _P]),
+        "qrfs_proposal_loss_grad": (S, [_P, _I64, _I64, _P, _P, _P, _P, _I32, _P, _P, _P]),
+        "qrfs_proposal_train": (S, [_P, _I64, _I64, _P, _P, _P, _P, _I64, _I64, _I32, _D,
+                                    ctypes.c_uint64, _P, _P]),
+        "qrfs_proposal_tabulate": (S, [_P, _D, _D, _I64, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                       _I32, _D, _P]),
+        "qrfs_proposal_get_table": (S, [_P, ctypes.POINTER(_I32), _P, _P, _P, _P, _P]),
+        "qrfs_proposal_set_table": (S, [_P, _I32, _P, _P, _P, _P, _P]),
+        "qrfs_proposal_save": (S, [_P, ctypes.c_char_p]),
+        "qrfs_proposal_load": (S, [_P, ctypes.c_char_p]),
+    })
     sig.update({
         "qrfs_batch_create": (S, [_P, _I64, ctypes.POINTER(BatchInstance), _I32,
                                   ctypes.POINTER(_P)]),
@@ -341,6 +369,117 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _check(load_library().qrfs_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Proposal:
+    """Learned proposal density of the frequency sampler (see qrfs.h)."""
+
+    def __init__(self, ctx, fmin, fmax, init_params):
+        lib = load_library()
+        self.ctx = ctx
+        self.fmin, self.fmax = float(fmin), float(fmax)
+        init = torch.as_tensor(init_params, dtype=torch.float32).to(ctx.device).contiguous()
+        if init.numel() != PROPOSAL_NPARAM:
+            raise ValueError(f"need {PROPOSAL_NPARAM} parameters")
+        h = _P()
+        _check(lib.qrfs_proposal_create(ctx.handle, self.fmin, self.fmax, _ptr(init),
+                                        ctypes.byref(h)))
+        torch.cuda.synchronize()
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def params(self):
+        out = torch.empty(PROPOSAL_NPARAM, dtype=torch.float32, device=self.ctx.device)
+        _check(load_library().qrfs_proposal_get_params(self._h, _ptr(out), _stream()))
+        return out
+
+    def set_params(self, prm):
+        prm = torch.as_tensor(prm, dtype=torch.float32).to(self.ctx.device).contiguous()
+        _check(load_library().qrfs_proposal_set_params(self._h, _ptr(prm), _stream()))
+        torch.cuda.synchronize()
+
+    def forward(self, ell, ctx4):
+        n = ell.numel()
+        out = torch.empty((n, 2), dtype=torch.float32, device=self.ctx.device)
+        _check(load_library().qrfs_proposal_forward(self._h, n, _dev_f64(ell, "ell"),
+                                                    _dev_f64(ctx4, "ctx4", 4 * n), _ptr(out),
+                                                    _stream()))
+        return out
+
+    def rows(self, plain_sampler, ctx4, m, r0, c_psd=0.0):
+        n_ctx = ctx4.numel() // 4
+        n = n_ctx * m
+        ell = torch.empty(n, dtype=torch.float64, device=self.ctx.device)
+        theta, h = torch.empty_like(ell), torch.empty_like(ell)
+        _check(load_library().qrfs_proposal_rows(self._h, ctypes.byref(plain_sampler), n_ctx, m,
+                                                 _dev_f64(ctx4, "ctx4"), r0, c_psd, _ptr(ell),
+                                                 _ptr(theta), _ptr(h), _stream()))
+        return ell, theta, h
+
+    def loss_grad(self, ctx4, ell, theta, h, G=64):
+        n_ctx = ctx4.numel() // 4
+        m = ell.numel() // n_ctx
+        grad = torch.empty(PROPOSAL_NPARAM, dtype=torch.float32, device=self.ctx.device)
+        loss = torch.empty(1, dtype=torch.float64, device=self.ctx.device)
+        _check(load_library().qrfs_proposal_loss_grad(
+            self._h, n_ctx, m, _dev_f64(ctx4, "ctx4"), _dev_f64(ell, "ell"),
+            _dev_f64(theta, "theta"), _dev_f64(h, "h"), G, _ptr(grad), _ptr(loss), _stream()))
+        return float(loss.item()), grad
+
+    def train(self, ctx4, ell, theta, h, steps, ctx_per_step=16, G=64, lr=1e-3, seed=0):
+        n_ctx = ctx4.numel() // 4
+        m = ell.numel() // n_ctx
+        log = torch.empty(steps, dtype=torch.float64, device=self.ctx.device)
+        _check(load_library().qrfs_proposal_train(
+            self._h, n_ctx, m, _dev_f64(ctx4, "ctx4"), _dev_f64(ell, "ell"),
+            _dev_f64(theta, "theta"), _dev_f64(h, "h"), ctx_per_step, steps, G, lr, seed,
+            _ptr(log), _stream()))
+        return log
+
+    def tabulate(self, D, L0, blen, bth, n_cells=256, beta=0.1):
+        import numpy as np
+        bl = np.ascontiguousarray(blen, dtype=np.float64)
+        bt = np.ascontiguousarray(bth, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(load_library().qrfs_proposal_tabulate(
+            self._h, D, L0, bl.size, bl.ctypes.data_as(dp), bt.ctypes.data_as(dp), n_cells, beta,
+            _stream()))
+
+    def get_table(self):
+        n = _I32(0)
+        lib = load_library()
+        _check(lib.qrfs_proposal_get_table(self._h, ctypes.byref(n), None, None, None, None,
+                                           _stream()))
+        t = [torch.empty(n.value, dtype=torch.float64, device=self.ctx.device) for _ in range(4)]
+        _check(lib.qrfs_proposal_get_table(self._h, ctypes.byref(n), *[_ptr(x) for x in t],
+                                           _stream()))
+        return t
+
+    def set_table(self, p, alpha, phi, cdf):
+        n = p.numel()
+        _check(load_library().qrfs_proposal_set_table(
+            self._h, n, _dev_f64(p, "p"), _dev_f64(alpha, "alpha", n), _dev_f64(phi, "phi", n),
+            _dev_f64(cdf, "cdf", n), _stream()))
+
+    def save(self, path):
+        _check(load_library().qrfs_proposal_save(self._h, str(path).encode()))
+
+    def load(self, path):
+        _check(load_library().qrfs_proposal_load(self._h, str(path).encode()))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().qrfs_proposal_destroy(self._h))
             self._h = None
 
     def __del__(self):

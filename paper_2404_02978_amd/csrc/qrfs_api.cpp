@@ -11,6 +11,13 @@
 #include "qrfs.h"
 #include "qrfs_internal.hpp"
 
+namespace qrfs {
+qrfs_status proposal_check_ready(const qrfs_proposal* p);
+hipError_t proposal_sample(const qrfs_proposal* p, uint64_t s0x, uint64_t s0y, uint64_t index,
+                           int64_t n_sets, int64_t K, double* fx, double* fy, double* area,
+                           hipStream_t st);
+}  // namespace qrfs
+
 struct qrfs_context {
     int device = 0;
     void* ws = nullptr;
@@ -103,8 +110,7 @@ qrfs_status check_ap(const qrfs_aperture* ap) {
 
 qrfs_status check_sampler(const qrfs_sampler* s) {
     if (!s) return fail(QRFS_ERR_INVALID_ARG, "sampler is NULL");
-    if (s->scheme == QRFS_SAMPLER_LEARNED)
-        return fail(QRFS_ERR_UNSUPPORTED, "learned sampler is not available in this build");
+    if (s->scheme == QRFS_SAMPLER_LEARNED) return qrfs::proposal_check_ready(s->proposal);
     if (s->scheme == QRFS_SAMPLER_R2_CARTESIAN) {
         if (s->N <= 0) return fail(QRFS_ERR_INVALID_ARG, "Cartesian N must be > 0 (got %d)", s->N);
         if (!(s->df > 0.0) || !std::isfinite(s->df))
@@ -143,6 +149,16 @@ qrfs_status check_sum_common(int64_t K, int64_t P, int64_t R, int64_t R_block,
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// R2 sampling with any scheme: sets [0, n_sets) starting at `index`
+hipError_t sample_any(const qrfs_sampler* s, uint64_t index, int64_t n_sets, int64_t K,
+                      double* fx, double* fy, double* area, hipStream_t st) {
+    if (s->scheme == QRFS_SAMPLER_LEARNED)
+        return qrfs::proposal_sample(s->proposal, s->seed_x, s->seed_y, index, n_sets, K, fx, fy,
+                                     area, st);
+    return qrfs::launch_sample(s->scheme, s->seed_x, s->seed_y, index, n_sets, K, s->N, s->df,
+                               s->fmin, s->fmax, fx, fy, area, st);
+}
 
 // Runs launch_sum over all sets, splitting the grid so no launch exceeds
 // 2^30 blocks.
@@ -299,8 +315,7 @@ qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s, int64_t 
     if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
     DeviceGuard g(ctx->device);
     if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
-    hipError_t e = qrfs::launch_sample(s->scheme, s->seed_x, s->seed_y, s->index, n_sets, K, s->N,
-                                       s->df, s->fmin, s->fmax, fx, fy, area, (hipStream_t)stream);
+    hipError_t e = sample_any(s, s->index, n_sets, K, fx, fy, area, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "sampler launch");
     s->index += (uint64_t)(n_sets * K);
     return ok();
@@ -400,9 +415,7 @@ qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
     for (int64_t s0 = 0; s0 < n_sets; s0 += spb) {
         int64_t s1 = s0 + spb < n_sets ? s0 + spb : n_sets;
         int64_t ns = s1 - s0;
-        hipError_t e = qrfs::launch_sample(s->scheme, s->seed_x, s->seed_y,
-                                           s->index + (uint64_t)(s0 * K), ns, K, s->N, s->df,
-                                           s->fmin, s->fmax, fx, fy, area, stream_);
+        hipError_t e = sample_any(s, s->index + (uint64_t)(s0 * K), ns, K, fx, fy, area, stream_);
         if (e != hipSuccess) return hip_fail(e, "sampler launch");
         e = qrfs::launch_weights(psd->model, c, psd->r0, psd->L0, 1, ap->D, ap->d, ns * K, fx, fy,
                                  area, w, stream_);

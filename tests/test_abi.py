@@ -29,7 +29,7 @@ def declared_symbols():
 def test_exports_every_declared_symbol(q):
     lib = q.load_library()
     names = declared_symbols()
-    assert len(names) >= 11
+    assert len(names) >= 30
     for n in names:
         assert hasattr(lib, n), n
 
@@ -82,9 +82,9 @@ def test_argument_checks_precede_device_use(q):
     st = lib.qrfs_sample_frequencies(None, ctypes.byref(s), 1, 8, p, p, p, None)
     assert st == q.ERR_INVALID_ARG
     s = q.logpolar_sampler(1e-3, 1e2)
-    s.scheme = q.SAMPLER_LEARNED
+    s.scheme = q.SAMPLER_LEARNED  # no proposal attached
     st = lib.qrfs_sample_frequencies(None, ctypes.byref(s), 1, 8, p, p, p, None)
-    assert st == q.ERR_UNSUPPORTED
+    assert st == q.ERR_INVALID_ARG and b"proposal" in lib.qrfs_last_error_detail()
     assert s.index == 0  # untouched on error
     # coefficients without rng
     st = lib.qrfs_synthesize_phase(None, 10, p, p, p, 4, p, p, 5, 5, None, None, 1, p, None)

@@ -321,10 +321,10 @@ def test_invalid_arguments_raise(q, ctx):
         ctx.sample_frequencies(q.logpolar_sampler(1.0, 0.5), 1, 10)
     assert e.value.status == q.ERR_INVALID_ARG
     s = q.logpolar_sampler(1e-3, 1e2)
-    s.scheme = q.SAMPLER_LEARNED
+    s.scheme = q.SAMPLER_LEARNED  # no proposal attached
     with pytest.raises(q.QrfsError) as e:
         ctx.sample_frequencies(s, 1, 10)
-    assert e.value.status == q.ERR_UNSUPPORTED
+    assert e.value.status == q.ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("precision", PRECS)
