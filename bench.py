@@ -55,7 +55,88 @@ def parse():
     ap.add_argument("--R-block", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle sample (0 disables it)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain-vs-chosen comparison (learned proposal)")
+    ap.add_argument("--workload", choices=["diffpiston", "phase", "large_screen", "batched"],
+                    default="diffpiston",
+                    help="diffpiston: the headline line; the others print their own report")
     return ap.parse_args()
+
+
+def _time_call(fn, reps=3):
+    """Median wall time in ms of fn() bracketed by device synchronisation."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def plain_vs_chosen(q, ctx, cfg, L0=25.0, R=100000, R_block=256):
+    """The differential-piston structure function at L0 with the plain
+    method (uniform-in-log R2, K = 65536, FP64 arithmetic) and with the
+    chosen configuration (learned proposal, K = 4096, FP32-class BF16x6 and
+    split-BF16), both at R realisations: error against the band-limited
+    analytic curve (RMS over the 32 baselines) and realisations/s of the
+    end-to-end call (sampling, weights, sums).  The proposal is trained on
+    the plain method's contributions first (not timed)."""
+    import numpy as np
+    import torch
+    import workloads
+    from oracle import analytic
+    dev = torch.device("cuda", 0)
+    bx = torch.as_tensor(cfg["bx"], dtype=torch.float64, device=dev)
+    by = torch.as_tensor(cfg["by"], dtype=torch.float64, device=dev)
+    ap = q.Aperture(cfg["D"], 0.0)
+    psd = q.psd(cfg["r0"], L0)
+    an = analytic.sf_band(cfg["bx"], cfg["r0"], L0, cfg["fmin"], cfg["fmax"], D=cfg["D"])
+
+    t0 = time.perf_counter()
+    c4 = torch.as_tensor(workloads.proposal_contexts(128, seed=0), device=dev)
+    prop = q.Proposal(ctx, cfg["fmin"], cfg["fmax"], workloads.mlp_init(0).astype(np.float32))
+    plain_rows = q.logpolar_sampler(cfg["fmin"], cfg["fmax"], index=1 << 40)
+    ell, theta, h = prop.rows(plain_rows, c4, 2048, cfg["r0"])
+    loss = prop.train(c4, ell, theta, h, steps=600, ctx_per_step=16, lr=2e-3, seed=1)
+    prop.tabulate(cfg["D"], L0, cfg["bx"], np.zeros(cfg["bx"].size))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    loss = loss.cpu().numpy()
+
+    out = {"L0": L0, "R": R, "R_block": R_block, "train_s": train_s,
+           "train_loss": [float(np.mean(loss[:20])), float(np.mean(loss[-20:]))]}
+
+    def run(name, sampler_fn, K, prec):
+        res = {}
+
+        def call():
+            res["sf"] = ctx.diff_piston_structure(psd, ap, bx, by, sampler_fn(), K, R, R_block,
+                                                  rng=q.Rng(7, 0, q.COEF_GAUSS_CS),
+                                                  precision=prec)[0]
+        ms = _time_call(call)
+        rel = res["sf"].cpu().numpy() / an - 1.0
+        out[name] = {"K": K, "precision": prec, "ms": ms, "realisations_per_s": R / (ms * 1e-3),
+                     "terms_per_s": R * K * cfg["bx"].size / (ms * 1e-3),
+                     "error_rms": float(np.sqrt(np.mean(rel ** 2))),
+                     "error_max": float(np.max(np.abs(rel)))}
+
+    run("plain_fp64_K65536", lambda: q.logpolar_sampler(cfg["fmin"], cfg["fmax"]), 65536,
+        q.PREC_FP64)
+    run("plain_bf16x6_K65536", lambda: q.logpolar_sampler(cfg["fmin"], cfg["fmax"]), 65536,
+        q.PREC_BF16X6)
+    run("plain_bf16x6_K4096", lambda: q.logpolar_sampler(cfg["fmin"], cfg["fmax"]), 4096,
+        q.PREC_BF16X6)
+    run("learned_bf16x6_K4096", lambda: q.learned_sampler(prop), 4096, q.PREC_BF16X6)
+    run("learned_splitbf16_K4096", lambda: q.learned_sampler(prop), 4096, q.PREC_SPLIT_BF16)
+    base = out["plain_fp64_K65536"]["realisations_per_s"]
+    for k in ("learned_bf16x6_K4096", "learned_splitbf16_K4096"):
+        out[k]["speedup_vs_plain_fp64"] = out[k]["realisations_per_s"] / base
+    prop.close()
+    return out
 
 
 def cpu_baseline(cfg, K, target_s):
@@ -95,6 +176,152 @@ def traffic_bytes(args, K, R, Rb):
     return t["bytes"].get(args.precision)
 
 
+def workload_phase(args):
+    """Phase screen, FP64: K = 1024 log-polar frequencies, 32 x 32 points over
+    1 m, R = 128; R_block = 1 (paper usage) and 128; empirical structure
+    function at the grid separations against the von Karman curve."""
+    import numpy as np
+    import torch
+    import paper_2404_02978_amd as q
+    import workloads
+    import oracle
+    from oracle import analytic
+    cfg = workloads.phase_fp64()
+    K, R = cfg["K"], cfg["R"]
+    ctx = q.Context(0)
+    px = torch.as_tensor(cfg["px"], device="cuda")
+    py = torch.as_tensor(cfg["py"], device="cuda")
+    out = {"workload": "phase screen FP64, K=1024, 32x32 points over 1 m, R=128", "runs": {}}
+    for Rb in (1, R):
+        n_sets = math.ceil(R / Rb)
+        res = {}
+
+        def call():
+            s = q.logpolar_sampler(cfg["fmin"], cfg["fmax"])
+            fx, fy, area = ctx.sample_frequencies(s, n_sets, K)
+            w = ctx.weights(q.psd(cfg["r0"], cfg["L0"]), fx, fy, area)
+            res["out"] = ctx.synthesize_phase(K, fx, fy, w, px, py, R, Rb,
+                                              rng=q.Rng(cfg["seed"], 0, 0), precision=q.PREC_FP64)
+            res["f"] = (fx, fy, w)
+        ms = _time_call(call)
+        ph = res["out"].cpu().numpy()
+        fx, fy, w = (t.cpu().numpy() for t in res["f"])
+        t = time.perf_counter()
+        ref = oracle.synthesize(fx, fy, w, cfg["px"], cfg["py"], R, Rb, K=K, seed=cfg["seed"])
+        oracle_s = time.perf_counter() - t
+        err = float(np.max(np.abs(ph - ref)) / np.sqrt(np.mean(ref ** 2)))
+        # empirical SF along x at separations of 1..31 pitches
+        g = ph.reshape(R, 32, 32)
+        seps = np.arange(1, 32)
+        emp = np.array([np.mean((g[:, :, s:] - g[:, :, :-s]) ** 2) for s in seps])
+        an = analytic.sf_band(seps / 31.0, cfg["r0"], cfg["L0"], cfg["fmin"], cfg["fmax"])
+        res_rel = emp / an - 1
+        out["runs"][f"R_block={Rb}"] = {
+            "ms": ms, "terms_per_s": R * K * 1024 / (ms * 1e-3), "max_err_vs_oracle": err,
+            "oracle_s": oracle_s, "oracle_terms_per_s": R * K * 1024 / oracle_s,
+            "sf_rel_err_rms": float(np.sqrt(np.mean(res_rel ** 2))),
+            "sf_rel_err_at": {f"{s / 31:.3f} m": float(r) for s, r in zip(seps[::6], res_rel[::6])}}
+    print(json.dumps(out), flush=True)
+
+
+def workload_large_screen(args):
+    """Large screen: K = 65536, 256 x 256 points over 8 m, R = 4096, one
+    frequency set; the contraction in split-BF16, BF16x6 and FP32, each
+    checked against the FP64 oracle on realisations 0..63 at 1024 sampled
+    points (max and RMS phase error in rad)."""
+    import numpy as np
+    import torch
+    import paper_2404_02978_amd as q
+    import workloads
+    cfg = workloads.large_screen(r0=0.1)
+    K, R = cfg["K"], cfg["R"]
+    P = cfg["px"].size
+    ctx = q.Context(0)
+    px = torch.as_tensor(cfg["px"], device="cuda")
+    py = torch.as_tensor(cfg["py"], device="cuda")
+    s = q.logpolar_sampler(cfg["fmin"], cfg["fmax"])
+    fx, fy, area = ctx.sample_frequencies(s, 1, K)
+    w = ctx.weights(q.psd(cfg["r0"], cfg["L0"]), fx, fy, area)
+    hfx, hfy, hw = (t.cpu().numpy() for t in (fx, fy, w))
+    cols = np.random.default_rng(0).choice(P, 1024, replace=False)
+    rows = list(range(64))
+    import oracle
+    t = time.perf_counter()
+    ref = oracle.synthesize(hfx, hfy, hw, cfg["px"][cols], cfg["py"][cols], 64, 64, K=K,
+                            seed=cfg["seed"])
+    oracle_s = time.perf_counter() - t
+    out = {"workload": "large screen, K=65536, 256x256 points over 8 m, R=4096, r0=0.1 m",
+           "flops": 4.0 * R * K * P, "oracle_subset_s": oracle_s, "runs": {}}
+    phase = torch.empty((R, P), dtype=torch.float32, device="cuda")
+    for name, prec, passes, peak in (("split_bf16", q.PREC_SPLIT_BF16, 3, 2500.0),
+                                     ("bf16x6", q.PREC_BF16X6, 6, 2500.0),
+                                     ("fp32", q.PREC_FP32, 1, 157.3)):
+        def call():
+            ctx.synthesize_phase(K, fx, fy, w, px, py, R, R, rng=q.Rng(cfg["seed"], 0, 0),
+                                 precision=prec, out=phase)
+        ms = _time_call(call, reps=2)
+        got = phase[:64][:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
+        d = got - ref
+        alg = 4.0 * R * K * P / (ms * 1e-3) / 1e12
+        out["runs"][name] = {"ms": ms, "terms_per_s": R * K * P / (ms * 1e-3),
+                             "algorithmic_tflops": alg, "mfma_frac": alg * passes / peak,
+                             "max_abs_err_rad": float(np.max(np.abs(d))),
+                             "rms_abs_err_rad": float(np.sqrt(np.mean(d * d))),
+                             "phase_rms_rad": float(np.sqrt(np.mean(ref * ref)))}
+    print(json.dumps(out), flush=True)
+
+
+def workload_batched(args):
+    """64 uneven instances (D ~ U[0.5, 39] m, grids 32^2..512^2 masked to the
+    disk, K = 2^11..2^16, L0 ~ U[10, 100] m, R = 256) in one persistent,
+    autotuned launch captured in a HIP graph; one instance checked against
+    the FP64 oracle on sampled outputs."""
+    import numpy as np
+    import torch
+    import paper_2404_02978_amd as q
+    import workloads
+    import oracle
+    ctx = q.Context(0)
+    inst = []
+    specs = workloads.batched()
+    for i, d in enumerate(specs):
+        inst.append(dict(psd=q.psd(d["r0"], d["L0"]),
+                         sampler=q.logpolar_sampler(workloads.FMIN, workloads.FMAX,
+                                                    index=i * (1 << 20)),
+                         K=d["K"], px=torch.as_tensor(d["px"], device="cuda"),
+                         py=torch.as_tensor(d["py"], device="cuda"), R=d["R"], R_block=d["R"],
+                         rng=q.Rng(d["seed"], d["counter"], 0)))
+    out = {"workload": "64 uneven phase-field instances, R=256 each", "runs": {}}
+    for name, prec in (("bf16x6", q.PREC_BF16X6), ("split_bf16", q.PREC_SPLIT_BF16)):
+        b = q.Batch(ctx, inst, precision=prec)
+        terms = b.info()["terms"]
+        first_ms = _time_call(lambda: b.execute(), reps=1)
+        tuned_ms = b.autotune()
+        eager_ms = _time_call(lambda: b.execute())
+        graph_ms = _time_call(lambda: b.execute(use_graph=True))
+        info = b.info()
+        out["runs"][name] = {"terms": terms, "n_items": info["n_items"], "shape": info["shape"],
+                             "first_call_ms": first_ms, "autotune_best_ms": tuned_ms,
+                             "eager_ms": eager_ms, "graph_ms": graph_ms,
+                             "terms_per_s_graph": terms / (graph_ms * 1e-3)}
+        if name == "bf16x6":
+            j = int(np.argmax([d["K"] for d in specs]))
+            d = specs[j]
+            fxo, fyo, ao = oracle.sample_logpolar(1, d["K"], workloads.FMIN, workloads.FMAX,
+                                                  index=j * (1 << 20))
+            wo = oracle.weights(fxo, fyo, ao, r0=d["r0"], L0=d["L0"])
+            cols = np.random.default_rng(1).choice(d["px"].size, min(256, d["px"].size),
+                                                   replace=False)
+            ref = oracle.synthesize(fxo, fyo, wo, d["px"][cols], d["py"][cols], 8, 8, K=d["K"],
+                                    seed=d["seed"], counter=d["counter"])
+            got = b.outputs[j][:8][:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
+            out["runs"][name]["check_instance"] = j
+            out["runs"][name]["max_err_vs_oracle"] = float(
+                np.max(np.abs(got - ref)) / np.sqrt(np.mean(ref * ref)))
+        b.close()
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration():
     """A plain 1 GiB device copy: FETCH_SIZE / WRITE_SIZE of this dispatch
     calibrate the HBM byte counters against a known traffic."""
@@ -112,6 +339,10 @@ def main():
     args = parse()
     if args.mode == "copy":
         copy_calibration()
+        return
+    if args.workload != "diffpiston":
+        {"phase": workload_phase, "large_screen": workload_large_screen,
+         "batched": workload_batched}[args.workload](args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -214,6 +445,10 @@ def main():
         fp32_ref = {"value": terms_per_step / (ms32 * 1e-3), "ms_per_step": ms32,
                     "kernel_ms": k32, "mfma_frac": flops / (k32 * 1e-3) / 1e12 / PEAKS["fp32"]}
 
+    compare = None
+    if not args.no_compare:
+        compare = plain_vs_chosen(q, ctx, cfg)
+
     cpu = None
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(cfg, K, args.cpu_seconds)
@@ -233,6 +468,7 @@ def main():
         "noise_floor_rms": math.sqrt(2.0 / R),
         "roofline": roof,
         "fp32_mfma_reference": fp32_ref,
+        "plain_vs_chosen": compare,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
