@@ -228,7 +228,9 @@ def workload_large_screen(args):
     """Large screen: K = 65536, 256 x 256 points over 8 m, R = 4096, one
     frequency set; the contraction in split-BF16, BF16x6 and FP32, each
     checked against the FP64 oracle on realisations 0..63 at 1024 sampled
-    points (max and RMS phase error in rad)."""
+    points (max and RMS phase error in rad).  Two-phase kernel (coefficient
+    tiles, then 256 x 256 MFMA tiles), and with --steps >= 2 the fused
+    kernel for comparison."""
     import numpy as np
     import torch
     import paper_2404_02978_amd as q
@@ -253,13 +255,21 @@ def workload_large_screen(args):
     out = {"workload": "large screen, K=65536, 256x256 points over 8 m, R=4096, r0=0.1 m",
            "flops": 4.0 * R * K * P, "oracle_subset_s": oracle_s, "runs": {}}
     phase = torch.empty((R, P), dtype=torch.float32, device="cuda")
-    for name, prec, passes, peak in (("split_bf16", q.PREC_SPLIT_BF16, 3, 2500.0),
-                                     ("bf16x6", q.PREC_BF16X6, 6, 2500.0),
-                                     ("fp32", q.PREC_FP32, 1, 157.3)):
+    for name, prec, passes, peak, path in (
+            ("split_bf16", q.PREC_SPLIT_BF16, 3, 2500.0, 2),
+            ("bf16x6", q.PREC_BF16X6, 6, 2500.0, 2),
+            ("fp32", q.PREC_FP32, 1, 157.3, 2),
+            ("split_bf16_fused", q.PREC_SPLIT_BF16, 3, 2500.0, 1),
+            ("bf16x6_fused", q.PREC_BF16X6, 6, 2500.0, 1),
+            ("fp32_fused", q.PREC_FP32, 1, 157.3, 1)):
+        if path == 1 and args.steps < 2:
+            continue
+        ctx.set_tuning(q.TUNE_WIDE_PATH, path)
+
         def call():
             ctx.synthesize_phase(K, fx, fy, w, px, py, R, R, rng=q.Rng(cfg["seed"], 0, 0),
                                  precision=prec, out=phase)
-        ms = _time_call(call, reps=2)
+        ms = _time_call(call, reps=3)
         got = phase[:64][:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
         d = got - ref
         alg = 4.0 * R * K * P / (ms * 1e-3) / 1e12

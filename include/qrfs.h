@@ -83,6 +83,25 @@ QRFS_API qrfs_status qrfs_context_create(qrfs_context** out, int32_t device);
 /* Synchronises the device and frees the workspace.  NULL is accepted. */
 QRFS_API qrfs_status qrfs_context_destroy(qrfs_context* ctx);
 
+/* Launch policy of a context (no paper passage: an implementation knob).
+ * QRFS_TUNE_WIDE_PATH selects how FP32 / split-BF16 / BF16x6 phase fields
+ * and pistons (qrfs_synthesize_phase, qrfs_piston, qrfs_diff_piston) are
+ * contracted: 0 (default) lets the library choose, 1 always uses the fused
+ * kernel (coefficients drawn in registers per column tile), 2 uses the
+ * two-phase kernel (coefficients drawn once into workspace tiles of at most
+ * 2 GiB, then 256 x 256 MFMA tiles) whenever the output fits it.
+ * QRFS_TUNE_RANGE_FREQS sets how many frequencies the two-phase kernel
+ * sums in FP32 before adding them into the output in FP32-class precisions
+ * (default 2048, rounded to whole chunks; 0 restores the default).
+ * QRFS_TUNE_TILE_BYTES caps the workspace the two-phase kernel stages its
+ * coefficient tiles in (default 2 GiB, 0 restores it); larger problems are
+ * cut into pieces of whole sets, or of 256-row blocks of one set.
+ * Errors: NULL context, unknown key, value out of range. */
+#define QRFS_TUNE_WIDE_PATH 1
+#define QRFS_TUNE_RANGE_FREQS 2
+#define QRFS_TUNE_TILE_BYTES 3
+QRFS_API qrfs_status qrfs_context_set_tuning(qrfs_context* ctx, int32_t key, int64_t value);
+
 /* ------------------------------------------------------------ parameters */
 /* Phase PSD (Sec. 4.1, Eq. 7 first factor), cycles/m:
  *   von Karman  W(f) = c r0^(-5/3) (f^2 + L0^-2)^(-11/6)

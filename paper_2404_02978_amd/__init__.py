@@ -92,6 +92,10 @@ def learned_sampler(proposal, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
 PROPOSAL_NPARAM = 17538
 
 
+TUNE_WIDE_PATH = 1
+TUNE_RANGE_FREQS = 2
+TUNE_TILE_BYTES = 3
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -114,6 +118,7 @@ def load_library():
         "qrfs_abi_version": (ctypes.c_int32, []),
         "qrfs_context_create": (S, [ctypes.POINTER(_P), _I32]),
         "qrfs_context_destroy": (S, [_P]),
+        "qrfs_context_set_tuning": (S, [_P, _I32, _I64]),
         "qrfs_sample_frequencies": (S, [_P, ctypes.POINTER(Sampler), _I64, _I64, _P, _P, _P, _P]),
         "qrfs_weights": (S, [_P, ctypes.POINTER(Psd), ctypes.POINTER(Aperture), _I64, _P, _P, _P,
                              _P, _P]),
@@ -221,6 +226,11 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+    def set_tuning(self, key, value):
+        """Launch policy: TUNE_WIDE_PATH (0 auto, 1 fused kernel, 2 two-phase
+        kernel), TUNE_RANGE_FREQS, TUNE_TILE_BYTES (see include/qrfs.h)."""
+        _check(load_library().qrfs_context_set_tuning(self._h, int(key), int(value)))
 
     # ---------------------------------------------------------------- API
     def sample_frequencies(self, sampler, n_sets, K):

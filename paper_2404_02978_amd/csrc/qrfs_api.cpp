@@ -22,6 +22,9 @@ struct qrfs_context {
     int device = 0;
     void* ws = nullptr;
     size_t ws_size = 0;
+    int wide_path = 0;          // QRFS_TUNE_WIDE_PATH
+    int64_t range_freqs = 2048;  // QRFS_TUNE_RANGE_FREQS
+    size_t tile_cap = (size_t)2 << 30;  // QRFS_TUNE_TILE_BYTES
 };
 
 namespace {
@@ -187,6 +190,87 @@ qrfs_status run_sum(int precision, int basis, int epi, qrfs::SumArgs a, int64_t 
     return QRFS_OK;
 }
 
+// Whether the two-phase kernel contracts this problem: MFMA precisions,
+// outputs wide enough to amortise the coefficient tiles, and enough
+// 256 x 256 tiles to fill the chip (or forced by the context).
+bool use_wide(const qrfs_context* ctx, int precision, int64_t P, int64_t R, int64_t R_block) {
+    if (precision == QRFS_PREC_FP64 || ctx->wide_path == 1) return false;
+    if (P > ((int64_t)1 << 22)) return false;  // 256 rows of output within 32-bit tile offsets
+    if (ctx->wide_path == 2) return true;
+    const int64_t tiles = cdiv(R, R_block) * cdiv(R_block, 256) * cdiv(P, 256);
+    return P >= 1024 && R_block >= 128 && tiles >= 512;
+}
+
+// Two-phase contraction (EPI_STORE) over all sets: per piece, the
+// coefficient tiles, then one contraction launch (FP32-class precisions sum
+// ranges of ctx->range_freqs frequencies in FP32 and add each into the
+// output; split-BF16 uses a single range).
+qrfs_status wide_sum(qrfs_context* ctx, int precision, int basis, qrfs::SumArgs a,
+                     int64_t n_sets, hipStream_t st) {
+    const int KCH = qrfs::wide_chunk(precision);
+    const int64_t nch = cdiv(a.K, KCH);
+    const int64_t nkv = nch * 2 * KCH;
+    const size_t row32 = qrfs::wide_frag_bytes_per_row32(precision, nkv);
+    const int64_t cts = cdiv(a.P, 256);
+    const int64_t rts_set = cdiv(a.R_block, 256);
+    // coefficient tiles take at most ctx->tile_cap of workspace per piece
+    // (one 256-row block of one set at least)
+    const size_t cap = ctx->tile_cap;
+    const size_t set_bytes = (size_t)rts_set * 8 * row32;
+    int64_t sets_piece = 1, rows_piece = a.R_block;
+    if (set_bytes <= cap) {
+        sets_piece = (int64_t)(cap / set_bytes);
+        const int64_t max_blocks = (int64_t)1 << 30;
+        if (sets_piece * rts_set * cts > max_blocks) sets_piece = max_blocks / (rts_set * cts);
+        if (sets_piece < 1) return fail(QRFS_ERR_INVALID_ARG, "problem too large for one set");
+        if (sets_piece > n_sets) sets_piece = n_sets;
+    } else {
+        int64_t tiles = (int64_t)(cap / (8 * row32));
+        rows_piece = (tiles < 1 ? 1 : tiles) * 256;
+    }
+    const size_t tile_bytes = align256((size_t)sets_piece * cdiv(rows_piece, 256) * 8 * row32);
+    qrfs_status s = ensure_workspace(ctx, tile_bytes + 256);
+    if (s) return s;
+    // accumulation ranges: whole K for split-BF16, else about
+    // ctx->range_freqs frequencies (an even number of chunks)
+    int64_t rch = precision == QRFS_PREC_SPLIT_BF16 ? nch : cdiv(ctx->range_freqs, KCH);
+    rch += rch & 1;
+    const double* fx0 = a.fx;
+    const double* fy0 = a.fy;
+    const double* w0 = a.w;
+    qrfs::WideArgs wa{};
+    wa.nkv = nkv;
+    wa.cts = cts;
+    wa.ctile = ctx->ws;
+    wa.sink = (float*)((char*)ctx->ws + tile_bytes);
+    for (int64_t s0 = 0; s0 < n_sets; s0 += sets_piece) {
+        const int64_t s1 = s0 + sets_piece < n_sets ? s0 + sets_piece : n_sets;
+        for (int64_t off = 0; off < a.R_block; off += rows_piece) {
+            // the last set may end before this row range
+            if (s1 - s0 == 1 && s0 * a.R_block + off >= a.R) break;
+            wa.s = a;
+            wa.s.set0 = s0;
+            wa.s.set1 = s1;
+            wa.s.fx = fx0 + s0 * a.K;
+            wa.s.fy = fy0 + s0 * a.K;
+            wa.s.w = w0 + s0 * a.K;
+            wa.row_off = off;
+            wa.rows = off + rows_piece < a.R_block ? rows_piece : a.R_block - off;
+            wa.rts = cdiv(wa.rows, 256);
+            wa.rt32 = wa.rts * 8;
+            hipError_t e = qrfs::launch_wide_coef(precision, wa, st);
+            if (e != hipSuccess) return hip_fail(e, "coefficient tile launch");
+            wa.ch0 = 0;
+            wa.ch1 = nch;
+            wa.range_ch = rch;
+            wa.accumulate = 0;
+            e = qrfs::launch_wide_sum(precision, basis, wa, st);
+            if (e != hipSuccess) return hip_fail(e, "two-phase contraction launch");
+        }
+    }
+    return QRFS_OK;
+}
+
 qrfs_status sum_entry(qrfs_context* ctx, int basis, int64_t K, const double* fx,
                       const double* fy, const double* w, int64_t P, const double* px,
                       const double* py, const double* apD, const double* apd, int64_t R,
@@ -230,7 +314,10 @@ qrfs_status sum_entry(qrfs_context* ctx, int basis, int64_t K, const double* fx,
     a.ksplit = 1;
     a.kspan = K;
     a.phi_part = nullptr;
-    s = run_sum(precision, basis, qrfs::EPI_STORE, a, cdiv(R, R_block), (hipStream_t)stream);
+    if (use_wide(ctx, precision, P, R, R_block))
+        s = wide_sum(ctx, precision, basis, a, cdiv(R, R_block), (hipStream_t)stream);
+    else
+        s = run_sum(precision, basis, qrfs::EPI_STORE, a, cdiv(R, R_block), (hipStream_t)stream);
     if (s) return s;
     return ok();
 }
@@ -281,6 +368,25 @@ qrfs_status qrfs_context_create(qrfs_context** out, int32_t device) {
     if (!c) return fail(QRFS_ERR_OUT_OF_MEMORY, "host allocation of the context");
     c->device = device;
     *out = c;
+    return ok();
+}
+
+qrfs_status qrfs_context_set_tuning(qrfs_context* ctx, int32_t key, int64_t value) {
+    if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    if (key == QRFS_TUNE_WIDE_PATH) {
+        if (value < 0 || value > 2)
+            return fail(QRFS_ERR_INVALID_ARG, "wide path must be 0, 1 or 2 (got %lld)", (long long)value);
+        ctx->wide_path = (int)value;
+    } else if (key == QRFS_TUNE_RANGE_FREQS) {
+        if (value < 0 || value > ((int64_t)1 << 33))
+            return fail(QRFS_ERR_INVALID_ARG, "range of %lld frequencies", (long long)value);
+        ctx->range_freqs = value == 0 ? 2048 : value;
+    } else if (key == QRFS_TUNE_TILE_BYTES) {
+        if (value < 0) return fail(QRFS_ERR_INVALID_ARG, "tile cap of %lld bytes", (long long)value);
+        ctx->tile_cap = value == 0 ? ((size_t)2 << 30) : (size_t)value;
+    } else {
+        return fail(QRFS_ERR_INVALID_ARG, "unknown tuning key %d", key);
+    }
     return ok();
 }
 

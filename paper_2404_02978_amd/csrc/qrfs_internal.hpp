@@ -49,6 +49,33 @@ struct SumArgs {
     float* phi_part;     // EPI_SFSUM, ksplit > 1: [ksplit][R][P] partial sums
 };
 
+// The two-phase contraction (wide point sets) over the sets [s.set0,
+// s.set1), rows [row_off, row_off + rows) of each set: launch_wide_coef
+// writes the coefficient tiles of all frequencies, then launch_wide_sum
+// contracts the frequency chunks [ch0, ch1) into 256 x 256 output tiles
+// (EPI_STORE, float output).
+struct WideArgs {
+    SumArgs s;        // fx / fy / w start at set s.set0
+    int64_t row_off;  // first row of each set covered by this launch
+    int64_t rows;     // rows of each set covered (the last set may hold fewer)
+    int64_t rt32;     // 32-row coefficient tiles per set in `ctile` (8 per block tile)
+    int64_t rts;      // 256-row block tiles per set
+    int64_t cts;      // 256-column block tiles
+    int64_t nkv;      // contraction length 2K padded to whole chunks
+    int64_t ch0, ch1; // chunks [ch0, ch1) of frequencies this launch contracts
+    int64_t range_ch; // chunks per accumulation range (even), each ending with
+                      // an add of the tile into the output
+    int32_t accumulate;  // 0: the first range stores its sums, 1: it adds them
+    void* ctile;      // coefficient tiles
+    float* sink;      // 64 floats that absorb the stores of elements outside the output
+};
+// frequencies per chunk of the two-phase kernel, and the bytes of
+// coefficient tiles per 32 rows for a padded contraction length nkv
+int wide_chunk(int precision);
+size_t wide_frag_bytes_per_row32(int precision, int64_t nkv);
+hipError_t launch_wide_coef(int precision, const WideArgs& wa, hipStream_t st);
+hipError_t launch_wide_sum(int precision, int basis, const WideArgs& wa, hipStream_t st);
+
 // How the structure-function sums are split for a problem: ksplit
 // frequency ranges per row tile, the FP32 partial-sum buffer it needs, and
 // the number of partial rows the final reduction reads.

@@ -4,12 +4,10 @@
 // split-BF16 MFMA), and the fixed-order structure-function reduction.
 #include "qrfs_device.hpp"
 #include "qrfs_internal.hpp"
+#include "qrfs_mfma.hpp"
 
 namespace qrfs {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------- sampler ----
 // One thread per frequency.  Point n = index + 1 + i of the R2 sequence
@@ -253,38 +251,6 @@ constexpr int KC = 32;
 constexpr int FLUSH = 2;
 constexpr int STR_F32 = 2 * KC + 4;  // floats per basis column (16-byte rows, skewed banks)
 constexpr int STR_H = 2 * KC + 8;    // 16-bit values per basis column
-
-__device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-}
-
-// x = hi + mid (+ lo) in bf16, each part the rounding of the remainder
-template <int NPL>
-__device__ __forceinline__ void split_bf16(float x, __bf16 part[NPL]) {
-    float r = x;
-#pragma unroll
-    for (int i = 0; i < NPL; ++i) {
-        __bf16 h = (__bf16)r;
-        part[i] = h;
-        r -= (float)h;
-    }
-}
-
-template <int BASIS>
-__device__ __forceinline__ void basis_pair(double t, double amp, float& cb, float& sb) {
-    float r = (float)frac_centered(t);
-    if (BASIS == BASIS_DIFF) {
-        float sh = __builtin_amdgcn_sinf(0.5f * r);  // sin(pi r)
-        cb = -2.0f * sh * sh;                         // cos(2 pi r) - 1
-        sb = __builtin_amdgcn_sinf(r);
-    } else {
-        cb = __builtin_amdgcn_cosf(r);
-        sb = __builtin_amdgcn_sinf(r);
-    }
-    float fa = (float)amp;
-    cb *= fa;
-    sb *= fa;
-}
 
 // CSRC: coefficient source, 0 = Gaussian cos/sin from Philox, 1 = Eq. 3
 // form from Philox, 2 = caller-supplied array (compile-time, so the integer
