@@ -393,10 +393,21 @@ typedef struct qrfs_batch qrfs_batch;
 QRFS_API qrfs_status qrfs_batch_create(qrfs_context* ctx, int64_t n,
                                        const qrfs_batch_instance* inst, int32_t precision,
                                        qrfs_batch** out);
-/* Times every candidate launch shape (rows and columns per block, resident
- * blocks per CU) on this batch and keeps the fastest; synchronises the
- * stream.  best_ms (host, may be NULL) receives its time in ms. */
+/* Launch shapes: 0-3 fused (each block draws its coefficients in registers;
+ * rows and columns per block, resident blocks per CU), 4 two-phase (each
+ * instance's coefficients drawn once into tiles the batch allocates on first
+ * use, at most 16 GiB in all, then 256 x 256 items on one block per CU).
+ * A new batch starts on shape 4 when its tiles fit, else on shape 0. */
+#define QRFS_BATCH_SHAPES 5
+/* Times every candidate launch shape on this batch and keeps the fastest;
+ * synchronises the stream.  best_ms (host, may be NULL) receives its time
+ * in ms. */
 QRFS_API qrfs_status qrfs_batch_autotune(qrfs_batch* b, void* stream, double* best_ms);
+/* Selects launch shape `shape` (an implementation knob, for callers that
+ * tune offline).  Errors: shape outside [0, QRFS_BATCH_SHAPES); the
+ * two-phase shape when its tiles exceed the cap (QRFS_ERR_UNSUPPORTED);
+ * allocation failure of the tiles (QRFS_ERR_OUT_OF_MEMORY). */
+QRFS_API qrfs_status qrfs_batch_set_shape(qrfs_batch* b, int32_t shape);
 /* Enqueues one execution on `stream`.  use_graph != 0: the first call
  * captures the whole sequence in a HIP graph (re-captured after an autotune
  * changes the shape), later calls replay it. */

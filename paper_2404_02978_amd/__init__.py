@@ -92,6 +92,9 @@ def learned_sampler(proposal, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
 PROPOSAL_NPARAM = 17538
 
 
+BATCH_SHAPES = 5
+BATCH_SHAPE_TWO_PHASE = 4
+
 TUNE_WIDE_PATH = 1
 TUNE_RANGE_FREQS = 2
 TUNE_TILE_BYTES = 3
@@ -158,6 +161,7 @@ def load_library():
                                   ctypes.POINTER(_P)]),
         "qrfs_batch_autotune": (S, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
         "qrfs_batch_execute": (S, [_P, _I32, _P]),
+        "qrfs_batch_set_shape": (S, [_P, _I32]),
         "qrfs_batch_info": (S, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32),
                                 ctypes.POINTER(ctypes.c_double)]),
         "qrfs_batch_destroy": (S, [_P]),
@@ -367,6 +371,10 @@ class Batch:
     def execute(self, use_graph=False):
         _check(load_library().qrfs_batch_execute(self._h, 1 if use_graph else 0, _stream()))
         return self.outputs
+
+    def set_shape(self, shape):
+        """Launch shape 0..BATCH_SHAPES-1 (4 = two-phase)."""
+        _check(load_library().qrfs_batch_set_shape(self._h, int(shape)))
 
     def info(self):
         n = _I64(0)

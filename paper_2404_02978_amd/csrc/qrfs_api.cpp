@@ -336,6 +336,7 @@ qrfs_status api_fail(qrfs_status s, const char* fmt, ...) {
     return s;
 }
 qrfs_status api_ok() { return ok(); }
+int64_t api_context_range_freqs(const qrfs_context* ctx) { return ctx->range_freqs; }
 int api_context_device(const qrfs_context* ctx) { return ctx->device; }
 }  // namespace qrfs
 

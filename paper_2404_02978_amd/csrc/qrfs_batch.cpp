@@ -19,7 +19,12 @@ namespace qrfs {
 qrfs_status api_fail(qrfs_status s, const char* fmt, ...);
 qrfs_status api_ok();
 int api_context_device(const qrfs_context* ctx);
+int64_t api_context_range_freqs(const qrfs_context* ctx);
 }  // namespace qrfs
+
+// Coefficient tiles of a two-phase batch take at most this much device
+// memory; larger batches are left to the fused shapes.
+static constexpr size_t kBatchTileCap = (size_t)16 << 30;
 
 struct qrfs_batch {
     int device = 0;
@@ -38,6 +43,13 @@ struct qrfs_batch {
     int n_items = 0;
     int shape = 0;
     int n_cu = 256;
+    // two-phase form: coefficient tiles of every instance and its launch
+    // arguments (allocated on first use of the two-phase shape)
+    int64_t range_freqs = 2048;
+    size_t tile_bytes = 0;  // 0: the two-phase shape is not available
+    void* tiles = nullptr;
+    qrfs::WideArgs* d_wargs = nullptr;
+    std::vector<qrfs::WideArgs> wargs;
     // graph
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -104,11 +116,68 @@ qrfs_status check_instance(const qrfs_batch_instance& in, int64_t i) {
     return QRFS_OK;
 }
 
+// Coefficient-tile bytes of instance i in the two-phase form (all sets).
+size_t wide_instance_bytes(const qrfs_batch* b, int i) {
+    const qrfs_batch_instance& in = b->inst[i];
+    const int KCH = qrfs::wide_chunk(b->precision);
+    const int64_t nkv = cdiv(in.K, KCH) * 2 * KCH;
+    const int64_t rt32 = cdiv(in.R_block, 256) * 8;
+    size_t bytes = (size_t)b->n_sets[i] * rt32 * qrfs::wide_frag_bytes_per_row32(b->precision, nkv);
+    return (bytes + 255) & ~(size_t)255;
+}
+
+// Allocates the coefficient tiles and the per-instance launch arguments of
+// the two-phase form (once).
+qrfs_status ensure_wide(qrfs_batch* b) {
+    if (b->tiles) return QRFS_OK;
+    if (!b->tile_bytes) return api_fail(QRFS_ERR_UNSUPPORTED, "two-phase shape unavailable");
+    hipError_t e = hipMalloc(&b->tiles, b->tile_bytes + 256);
+    if (e == hipSuccess) e = hipMalloc(&b->d_wargs, sizeof(qrfs::WideArgs) * b->n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (b->tiles) (void)hipFree(b->tiles);
+        b->tiles = nullptr;
+        return api_fail(QRFS_ERR_OUT_OF_MEMORY, "coefficient tiles: %s", hipGetErrorString(e));
+    }
+    const int KCH = qrfs::wide_chunk(b->precision);
+    char* p = (char*)b->tiles;
+    b->wargs.clear();
+    for (int i = 0; i < b->n; ++i) {
+        const qrfs_batch_instance& in = b->inst[i];
+        qrfs::WideArgs wa{};
+        wa.s = b->args[i];
+        const int64_t nch = cdiv(in.K, KCH);
+        wa.row_off = 0;
+        wa.rows = in.R_block;
+        wa.rts = cdiv(in.R_block, 256);
+        wa.rt32 = wa.rts * 8;
+        wa.cts = cdiv(in.P, 256);
+        wa.nkv = nch * 2 * KCH;
+        wa.ch0 = 0;
+        wa.ch1 = nch;
+        int64_t rch = b->precision == QRFS_PREC_SPLIT_BF16 ? nch : cdiv(b->range_freqs, KCH);
+        wa.range_ch = rch + (rch & 1);
+        wa.accumulate = 0;
+        wa.ctile = p;
+        wa.sink = (float*)((char*)b->tiles + b->tile_bytes);
+        p += wide_instance_bytes(b, i);
+        b->wargs.push_back(wa);
+    }
+    e = hipMemcpy(b->d_wargs, b->wargs.data(), sizeof(qrfs::WideArgs) * b->n,
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hfail(e, "two-phase instance upload");
+    return QRFS_OK;
+}
+
 // Work list for the current shape: every (instance, set, row tile, column
 // tile), sorted by decreasing cost (rows x columns x K), stable.
 qrfs_status build_items(qrfs_batch* b) {
     qrfs::BatchShape sh = qrfs::batch_shape(b->precision, b->shape);
-    const int64_t MT = 32 * sh.MW * 4, NT = 32 * sh.NB;
+    if (sh.wide) {
+        qrfs_status s = ensure_wide(b);
+        if (s) return s;
+    }
+    const int64_t MT = sh.wide ? 256 : 32 * sh.MW * 4, NT = sh.wide ? 256 : 32 * sh.NB;
     struct Rec {
         double cost;
         qrfs::BatchItem it;
@@ -165,8 +234,18 @@ qrfs_status enqueue(qrfs_batch* b, hipStream_t st) {
     }
     qrfs::BatchShape sh = qrfs::batch_shape(b->precision, b->shape);
     int blocks = std::max(1, std::min(b->n_items, b->n_cu * sh.blocks_per_cu));
-    hipError_t e = qrfs::launch_batch(b->precision, sh, b->d_args, b->d_items, b->n_items,
-                                      b->d_counter, blocks, st);
+    hipError_t e;
+    if (sh.wide) {
+        for (int i = 0; i < b->n; ++i) {
+            e = qrfs::launch_wide_coef(b->precision, b->wargs[i], st);
+            if (e != hipSuccess) return hfail(e, "coefficient tile launch");
+        }
+        e = qrfs::launch_wide_batch(b->precision, b->d_wargs, b->d_items, b->n_items,
+                                    b->d_counter, blocks, st);
+    } else {
+        e = qrfs::launch_batch(b->precision, sh, b->d_args, b->d_items, b->n_items, b->d_counter,
+                               blocks, st);
+    }
     if (e != hipSuccess) return hfail(e, "persistent launch");
     return QRFS_OK;
 }
@@ -260,7 +339,13 @@ qrfs_status qrfs_batch_create(qrfs_context* ctx, int64_t n, const qrfs_batch_ins
         qrfs_batch_destroy(b);
         return hfail(e, "instance upload");
     }
-    b->shape = 0;
+    // the two-phase shape is offered when its coefficient tiles fit the cap;
+    // it is the starting shape then
+    b->range_freqs = qrfs::api_context_range_freqs(ctx);
+    size_t tb = 0;
+    for (int i = 0; i < b->n; ++i) tb += wide_instance_bytes(b, i);
+    b->tile_bytes = tb <= kBatchTileCap ? tb : 0;
+    b->shape = b->tile_bytes ? qrfs::batch_shape_count(b->precision) - 1 : 0;
     qrfs_status s = build_items(b);
     if (s) {
         qrfs_batch_destroy(b);
@@ -320,6 +405,7 @@ qrfs_status qrfs_batch_autotune(qrfs_batch* b, void* stream, double* best_ms) {
     float best_t = 1e30f;
     qrfs_status s = QRFS_OK;
     for (int id = 0; id < qrfs::batch_shape_count(b->precision) && !s; ++id) {
+        if (qrfs::batch_shape(b->precision, id).wide && !b->tile_bytes) continue;
         b->shape = id;
         if ((s = build_items(b))) break;
         if ((s = enqueue(b, st))) break;  // warm-up
@@ -348,6 +434,26 @@ qrfs_status qrfs_batch_autotune(qrfs_batch* b, void* stream, double* best_ms) {
     return api_ok();
 }
 
+qrfs_status qrfs_batch_set_shape(qrfs_batch* b, int32_t shape) {
+    if (!b) return api_fail(QRFS_ERR_INVALID_ARG, "batch is NULL");
+    if (shape < 0 || shape >= qrfs::batch_shape_count(b->precision))
+        return api_fail(QRFS_ERR_INVALID_ARG, "shape %d out of range", shape);
+    if (qrfs::batch_shape(b->precision, shape).wide && !b->tile_bytes)
+        return api_fail(QRFS_ERR_UNSUPPORTED, "two-phase shape: coefficient tiles exceed %zu bytes",
+                        kBatchTileCap);
+    Guard g(b->device);
+    if (!g.okay) return api_fail(QRFS_ERR_DEVICE, "cannot select device %d", b->device);
+    const int prev = b->shape;
+    b->shape = shape;
+    qrfs_status s = build_items(b);
+    if (s) {
+        b->shape = prev;
+        (void)build_items(b);
+        return s;
+    }
+    return api_ok();
+}
+
 qrfs_status qrfs_batch_info(const qrfs_batch* b, int64_t* n_items, int32_t* shape, double* terms) {
     if (!b) return api_fail(QRFS_ERR_INVALID_ARG, "batch is NULL");
     if (n_items) *n_items = b->n_items;
@@ -367,6 +473,8 @@ qrfs_status qrfs_batch_destroy(qrfs_batch* b) {
         if (b->d_args) (void)hipFree(b->d_args);
         if (b->d_items) (void)hipFree(b->d_items);
         if (b->d_counter) (void)hipFree(b->d_counter);
+        if (b->tiles) (void)hipFree(b->tiles);
+        if (b->d_wargs) (void)hipFree(b->d_wargs);
     }
     delete b;
     return api_ok();

@@ -96,9 +96,10 @@ struct BatchItem {
 };
 
 // Launch shape of the persistent batch kernel: rows per wave (32 MW),
-// columns per block (32 NB), resident blocks per CU of the grid.
+// columns per block (32 NB), resident blocks per CU of the grid; `wide`
+// selects the two-phase form (coefficient tiles, 256 x 256 items).
 struct BatchShape {
-    int MW, NB, blocks_per_cu;
+    int MW, NB, blocks_per_cu, wide;
 };
 int batch_shape_count(int precision);
 BatchShape batch_shape(int precision, int id);
@@ -108,6 +109,13 @@ BatchShape batch_shape(int precision, int id);
 hipError_t launch_batch(int precision, BatchShape shape, const SumArgs* inst,
                         const BatchItem* items, int n_items, unsigned* counter, int n_blocks,
                         hipStream_t st);
+
+// Resets the work counter and launches the persistent two-phase kernel
+// (n_blocks blocks) over items[0 .. n_items) of the instances `inst`
+// (device array; coefficient tiles already written).
+hipError_t launch_wide_batch(int precision, const WideArgs* inst, const BatchItem* items,
+                             int n_items, unsigned* counter, int n_blocks, hipStream_t st);
+hipError_t launch_reset_counter(unsigned* counter, hipStream_t st);
 
 // squares of the K-range partial sums, summed per column over blocks of
 // rows: partial[ceil(R/256)][P][2]

@@ -831,10 +831,17 @@ hipError_t launch_sum(int precision, int basis, int epi, const SumArgs& a, hipSt
 
 // Batch launch shapes the autotuner chooses from: (MW, NB) per precision
 // and the number of resident blocks per CU of the persistent grid.
-static const BatchShape kShapesF32[] = {{1, 2, 2}, {1, 2, 3}, {1, 1, 4}, {1, 2, 4}};
-static const BatchShape kShapesSplit[] = {{2, 2, 1}, {2, 2, 2}, {1, 2, 2}, {1, 2, 3}};
+static const BatchShape kShapesF32[] = {{1, 2, 2, 0}, {1, 2, 3, 0}, {1, 1, 4, 0}, {1, 2, 4, 0},
+                                        {0, 0, 1, 1}};
+static const BatchShape kShapesSplit[] = {{2, 2, 1, 0}, {2, 2, 2, 0}, {1, 2, 2, 0}, {1, 2, 3, 0},
+                                          {0, 0, 1, 1}};
 
-int batch_shape_count(int precision) { return precision == 1 ? 4 : 4; }
+int batch_shape_count(int precision) { return precision == 1 ? 5 : 5; }
+
+hipError_t launch_reset_counter(unsigned* counter, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+    return hipGetLastError();
+}
 
 BatchShape batch_shape(int precision, int id) {
     return precision == 1 ? kShapesF32[id] : kShapesSplit[id];

@@ -398,24 +398,14 @@ struct WideTile {
     }
 };
 
+// One 256 x 256 output tile: rows [rt] of set sl, columns [ct], all
+// chunks of wa; every thread of the block calls it (it synchronises).
 template <int PREC, int BASIS, int WV>
-__global__ __launch_bounds__(64 * WV) void k_wide(WideArgs wa) {
-    __shared__ WideSmem<PREC> sm;
+__device__ __forceinline__ void wide_tile_run(WideSmem<PREC>& sm, const WideArgs& wa, int64_t sl,
+                                              int64_t rt, int64_t ct) {
     using Tile = WideTile<PREC, BASIS, WV>;
     typedef typename Tile::Frag Frag;
     constexpr int NSTEP = Tile::NSTEP, NPL = Tile::NPL, MB = Tile::MB, NPART = Tile::NPART;
-
-    // XCD-aware order: consecutive tiles (same row panel, successive column
-    // tiles) go to the blocks one XCD runs (blocks are dealt to the 8 XCDs
-    // round robin)
-    const int64_t nblk = gridDim.x;
-    const int64_t b = blockIdx.x;
-    const int64_t per = nblk / 8;
-    const int64_t t = b < 8 * per ? (b % 8) * per + b / 8 : b;
-    const int64_t ct = t % wa.cts;
-    const int64_t rt = (t / wa.cts) % wa.rts;
-    const int64_t sl = t / (wa.cts * wa.rts);
-
     Tile T(sm, wa, sl, rt, ct);
     Frag F[2][MB][NPL];
     double fq0[3], fq1[3], fq2[3];
@@ -445,6 +435,47 @@ __global__ __launch_bounds__(64 * WV) void k_wide(WideArgs wa) {
             }
         }
         T.store(wa, rt, ct, wa.accumulate || rs > 0);
+    }
+}
+
+template <int PREC, int BASIS, int WV>
+__global__ __launch_bounds__(64 * WV) void k_wide(WideArgs wa) {
+    __shared__ WideSmem<PREC> sm;
+    // XCD-aware order: consecutive tiles (same row panel, successive column
+    // tiles) go to the blocks one XCD runs (blocks are dealt to the 8 XCDs
+    // round robin)
+    const int64_t nblk = gridDim.x;
+    const int64_t b = blockIdx.x;
+    const int64_t per = nblk / 8;
+    const int64_t t = b < 8 * per ? (b % 8) * per + b / 8 : b;
+    const int64_t ct = t % wa.cts;
+    const int64_t rt = (t / wa.cts) % wa.rts;
+    const int64_t sl = t / (wa.cts * wa.rts);
+    wide_tile_run<PREC, BASIS, WV>(sm, wa, sl, rt, ct);
+}
+
+// Persistent batch of uneven phase-field instances (two-phase form): one
+// block per CU pulls work items (instance, set, 256-row tile, 256-column
+// tile) from a global counter until the list is exhausted; items come
+// longest first.  The counter is advanced with a vector atomic by one lane,
+// and every wave reaches the exit test on each iteration.
+template <int PREC, int WV>
+__global__ __launch_bounds__(64 * WV) void k_wide_batch(const WideArgs* __restrict__ inst,
+                                                        const BatchItem* __restrict__ items,
+                                                        int n_items,
+                                                        unsigned* __restrict__ counter) {
+    __shared__ WideSmem<PREC> sm;
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (it >= n_items) break;
+        const BatchItem w = items[it];
+        const WideArgs wa = inst[w.inst];
+        wide_tile_run<PREC, BASIS_PHASE, WV>(sm, wa, w.set, w.rt, w.ct);
+        __syncthreads();
     }
 }
 
@@ -489,6 +520,25 @@ static hipError_t launch_sum_p(int basis, const WideArgs& wa, hipStream_t st) {
     if (basis == BASIS_PHASE) return launch_sum_t<PREC, BASIS_PHASE>(wa, st);
     if (basis == BASIS_PISTON) return launch_sum_t<PREC, BASIS_PISTON>(wa, st);
     return launch_sum_t<PREC, BASIS_DIFF>(wa, st);
+}
+
+template <int PREC>
+static hipError_t launch_wide_batch_t(const WideArgs* inst, const BatchItem* items, int n_items,
+                                      unsigned* counter, int n_blocks, hipStream_t st) {
+    constexpr int WV = QRFS_WIDE_WAVES;
+    hipLaunchKernelGGL((k_wide_batch<PREC, WV>), dim3((unsigned)n_blocks), dim3(64 * WV), 0, st,
+                       inst, items, n_items, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_batch(int precision, const WideArgs* inst, const BatchItem* items,
+                             int n_items, unsigned* counter, int n_blocks, hipStream_t st) {
+    hipError_t e = launch_reset_counter(counter, st);
+    if (e != hipSuccess) return e;
+    if (precision == 1) return launch_wide_batch_t<1>(inst, items, n_items, counter, n_blocks, st);
+    if (precision == 2) return launch_wide_batch_t<2>(inst, items, n_items, counter, n_blocks, st);
+    if (precision == 3) return launch_wide_batch_t<3>(inst, items, n_items, counter, n_blocks, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_wide_sum(int precision, int basis, const WideArgs& wa, hipStream_t st) {

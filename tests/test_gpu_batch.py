@@ -72,9 +72,33 @@ def test_batch_matches_oracle(q, ctx, precision, R_block_div):
     b.close()
 
 
-def test_batch_graph_replays(q, ctx):
+@pytest.mark.parametrize("precision", [1, 2, 3])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
+def test_batch_every_shape(q, ctx, precision, shape):
+    """Each launch shape (fused 0-3, two-phase 4) against the oracle, with
+    several sets per instance."""
+    inst, refs = instances(q, 3)
+    b = q.Batch(ctx, inst, precision=precision)
+    b.set_shape(shape)
+    assert b.info()["shape"] == shape
+    check(b.execute(), refs, TOL[precision], f"shape {shape} p{precision}")
+    b.close()
+
+
+def test_batch_two_phase_is_default(q, ctx):
+    inst, _ = instances(q, 1)
+    b = q.Batch(ctx, inst, precision=2)
+    assert b.info()["shape"] == q.BATCH_SHAPE_TWO_PHASE
+    with pytest.raises(q.QrfsError):
+        b.set_shape(q.BATCH_SHAPES)
+    b.close()
+
+
+@pytest.mark.parametrize("shape", [0, 4])
+def test_batch_graph_replays(q, ctx, shape):
     inst, refs = instances(q, 2)
     b = q.Batch(ctx, inst, precision=3)
+    b.set_shape(shape)
     eager = [o.clone() for o in b.execute()]
     torch.cuda.synchronize()
     for rep in range(3):
