@@ -31,14 +31,25 @@ if ROOT not in sys.path:
 
 METRIC = "synthesized terms/s (R·K·P) and realisations/s at fixed error, plain vs chosen"
 PEAKS = {"fp32": 157.3, "split_bf16": 2500.0, "bf16x6": 2500.0, "fp64": 78.6}  # dense TFLOP/s
+# vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane op per cycle
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# algorithmic vector ops of the generator per coefficient: Philox4x32-10
+# (10 rounds x (2 products + 4 xor) per 4 words = 15), uniform (3),
+# Box-Muller (4 per coefficient), operand split (5.5 three-way, 3 two-way)
+OPS_PER_COEF = {"bf16x6": 27.5, "split_bf16": 25.0}
+# per (frequency, column, row tile): FP64 product and range reduction (5),
+# difference basis sin, sin^2 (5), amplitude (2), split of 2 values
+OPS_PER_BASIS = {"bf16x6": 23.0, "split_bf16": 18.0}
 PREC_IDS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "bf16x6": 3}
 # MFMA FLOPs executed per algorithmic flop (split-BF16 runs 3 products, BF16x6 six)
 MFMA_PASSES = {"fp32": 1, "split_bf16": 3, "bf16x6": 6, "fp64": 1}
 DTYPES = {"fp32": "f32", "split_bf16": "bf16x3", "bf16x6": "bf16x6", "fp64": "f64"}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
 # a 1 GiB copy (x2.0 / x1.0), valid only for the kernel source they were taken with
-TRAFFIC = {"sha256_prefix": "8c88cf630cc61531", "K": 16384, "R": 100000, "R_block": 256,
-           "bytes": {"bf16x6": 2.564e8, "fp32": 2.564e8}}
+# sources the structure-function kernels are built from (hashed together)
+KERNEL_SOURCES = ("qrfs_kernels.hip", "qrfs_mfma.hpp", "qrfs_device.hpp", "qrfs_internal.hpp")
+TRAFFIC = {"sha256_prefix": "f330a800edf5bd91", "K": 16384, "R": 100000, "R_block": 256,
+           "bytes": {"bf16x6": 2.5635e8, "fp32": 2.5635e8}}
 
 
 def parse():
@@ -168,8 +179,10 @@ def traffic_bytes(args, K, R, Rb):
     """Measured HBM bytes per launch, or None when the kernel source or the
     problem differs from the one the counters were taken on."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2404_02978_amd", "csrc", "qrfs_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2404_02978_amd", "csrc", f), "rb").read())
+    sha = h.hexdigest()[:16]
     t = TRAFFIC
     if sha != t["sha256_prefix"] or (K, R, Rb) != (t["K"], t["R"], t["R_block"]):
         return None
@@ -428,15 +441,26 @@ def main():
     flops = 4.0 * R * K * nB  # algorithmic: 2 MACs (cos and sin term) per (r, k, b)
     achieved = flops / (avg_kernel_ms * 1e-3) / 1e12
     peak = PEAKS[args.precision]
-    roof = {"bound": "mfma", "achieved": achieved * MFMA_PASSES[args.precision], "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": achieved * MFMA_PASSES[args.precision] / peak,
-            "traffic": traffic_bytes(args, K, R, Rb),
-            "algorithmic_tflops": achieved,
-            "kernel": "k_sum_mfma<diff, sfsum> + k_sfsum_rows + k_reduce_sf (event-timed per "
-                      "launch)",
-            "kernel_ms": avg_kernel_ms,
-            "flops_per_launch": flops, "mfma_passes": MFMA_PASSES[args.precision]}
+    mfma_view = {"achieved": achieved * MFMA_PASSES[args.precision], "peak": peak,
+                 "unit": "TFLOP/s", "frac": achieved * MFMA_PASSES[args.precision] / peak,
+                 "algorithmic_tflops": achieved, "flops_per_launch": flops,
+                 "mfma_passes": MFMA_PASSES[args.precision]}
+    kern = ("k_sum_mfma<diff, sfsum> + k_sfsum_rows + k_reduce_sf (event-timed per launch on "
+            "the stream they run on)")
+    if args.precision in OPS_PER_COEF:
+        # generator-bound: the coefficients are drawn by the vector ALU while
+        # the bf16 MFMAs run beside it on the matrix cores
+        row_tiles = math.ceil(Rb / 128)
+        ops = (R * 2.0 * K * OPS_PER_COEF[args.precision]
+               + n_sets * row_tiles * K * (nB + 1) * OPS_PER_BASIS[args.precision])
+        a_ops = ops / (avg_kernel_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": a_ops, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                "frac": a_ops / VALU_PEAK_TOPS, "traffic": traffic_bytes(args, K, R, Rb),
+                "ops_per_launch": ops, "kernel": kern, "kernel_ms": avg_kernel_ms,
+                "mfma_view": mfma_view}
+    else:
+        roof = dict(mfma_view, bound="mfma", traffic=traffic_bytes(args, K, R, Rb), kernel=kern,
+                    kernel_ms=avg_kernel_ms)
 
     # the same workload with the FP32 MFMA contraction, for reference
     fp32_ref = None
