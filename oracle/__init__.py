@@ -53,6 +53,9 @@ def _load():
                                  _u64, _i32, _p, _p]),
         "oracle_diff_piston_sf": (None, [_i64, _p, _p, _p, _i64, _p, _p, _i64, _i64, _u64,
                                          _u64, _i32, _p, _p]),
+        "oracle_temporal_sf": (None, [_p, _i64, _i64, _p, _p]),
+        "oracle_temporal_experiment": (None, [_i64, _p, _p, _p, _p, _p, _p, _d, _i64, _i64,
+                                              _i64, _u64, _u64, _i32, _p, _p]),
     }
     sig.update({
         "oracle_mlp_param_count": (_i64, [ctypes.c_int]),
@@ -197,6 +200,32 @@ def diff_piston_sf(fx, fy, w, bx, by, R, R_block, K=None, seed=0, counter=0,
     se = np.zeros(bx.size)
     _load().oracle_diff_piston_sf(K, _ptr(fx), _ptr(fy), _ptr(w), bx.size, _ptr(bx), _ptr(by),
                                   R, R_block, seed, counter, mode, _ptr(sf), _ptr(se))
+    return sf, se
+
+
+def temporal_sf(pist):
+    """Time-lag structure function of the differential piston (Sec. 4.4):
+    pist [R][2][M] pistons of telescopes 1, 2 at t_m = m dt; returns
+    (sf[M], sf_stderr[M]) averaged over pairs and realisations."""
+    pist = np.ascontiguousarray(np.asarray(pist, dtype=np.float64))
+    R, two, M = pist.shape
+    assert two == 2
+    sf, se = np.zeros(M), np.zeros(M)
+    _load().oracle_temporal_sf(_ptr(pist), R, M, _ptr(sf), _ptr(se))
+    return sf, se
+
+
+def temporal_experiment(fx, fy, w, c1, c2, v, dt, M, R, R_block, K=None, seed=0, counter=0,
+                        mode=COEF_GAUSS_CS):
+    """Frozen-flow pistons at c1 - v t_m and c2 - v t_m (t_m = m dt) with the
+    aperture-filtered weights w, then temporal_sf."""
+    fx, fy, w = map(_f64, (fx, fy, w))
+    c1, c2, v = (_f64(np.asarray(x, dtype=np.float64)) for x in (c1, c2, v))
+    K = fx.size if K is None else K
+    sf, se = np.zeros(M), np.zeros(M)
+    _load().oracle_temporal_experiment(K, _ptr(fx), _ptr(fy), _ptr(w), _ptr(c1), _ptr(c2),
+                                       _ptr(v), float(dt), M, R, R_block, seed, counter, mode,
+                                       _ptr(sf), _ptr(se))
     return sf, se
 
 

@@ -138,3 +138,55 @@ def diff_piston_sf(B, r0, L0, D, d=0.0, c=None, model=1, fmin=1e-7, fmax=None):
     Default band: effectively untruncated."""
     fmax = fmax if fmax is not None else 40.0 / D
     return sf_band(B, r0, L0, fmin, fmax, c=c, model=model, D=D, d=d)
+
+
+def temporal_sf(tau, B, v, r0, L0, D, d=0.0, c=None, model=1, fmin=1e-7, fmax=None):
+    """Frozen-flow structure function of the differential piston between two
+    equal apertures separated by the vector B, wind velocity vector v, at
+    lags tau (Sec. 4.4): with u = v tau and the piston covariance C,
+    D(tau) = 4 C(0) - 4 C(|B|) - 4 C(|u|) + 2 C(|B - u|) + 2 C(|B + u|)
+    (the variance of dp(t + tau) - dp(t), dp = p(c1 - v t) - p(c2 - v t))."""
+    B = np.asarray(B, dtype=float)
+    v = np.asarray(v, dtype=float)
+    tau = np.atleast_1d(np.asarray(tau, dtype=float))
+    kw = dict(r0=r0, L0=L0, D=D, d=d, c=c, model=model, fmin=fmin, fmax=fmax)
+    C0 = piston_cov(0.0, **kw)[0]
+    CB = piston_cov(np.hypot(*B), **kw)[0]
+    out = []
+    for t in tau:
+        u = v * t
+        Cu = piston_cov(np.hypot(*u), **kw)[0]
+        Cm = piston_cov(np.hypot(*(B - u)), **kw)[0]
+        Cp = piston_cov(np.hypot(*(B + u)), **kw)[0]
+        out.append(4.0 * C0 - 4.0 * CB - 4.0 * Cu + 2.0 * Cm + 2.0 * Cp)
+    return np.array(out)
+
+
+def temporal_sf_square(tau, B, v, r0, L0, D, d=0.0, half_width=0.25, c=None, model=1, n=801):
+    """Exact expectation of the temporal estimator when the frequencies fill
+    the square [-half_width, half_width)^2 (the Cartesian R2 domain of Eq. 5,
+    N df = 2 fmax): the double integral of W F^2 16 sin^2(pi f.B)
+    sin^2(pi f.v tau) over the square, by a tensor Gauss-Legendre rule on
+    sub-squares (the integrand is smooth; W is finite for von Karman)."""
+    c = psd_constant() if c is None else c
+    B = np.asarray(B, dtype=float)
+    v = np.asarray(v, dtype=float)
+    tau = np.atleast_1d(np.asarray(tau, dtype=float))
+    # n x n panels of a 6-point rule, summed one strip of rows at a time
+    xg, wg = np.polynomial.legendre.leggauss(6)
+    edges = np.linspace(-half_width, half_width, n + 1)
+    h = np.diff(edges)
+    nodes = (edges[:-1, None] + 0.5 * h[:, None] * (xg[None, :] + 1.0)).ravel()
+    wts = (0.5 * h[:, None] * wg[None, :]).ravel()
+    out = np.zeros(tau.size)
+    step = 256
+    for i0 in range(0, nodes.size, step):
+        FX, FY = np.meshgrid(nodes[i0:i0 + step], nodes, indexing="ij")
+        WW = np.outer(wts[i0:i0 + step], wts)
+        f = np.maximum(np.hypot(FX, FY), 1e-300)
+        base = (WW * _psd(f, r0, L0, c, model) * aperture_filter(f, D, d) ** 2
+                * np.sin(np.pi * (FX * B[0] + FY * B[1])) ** 2)
+        for j, t in enumerate(tau):
+            u = v * t
+            out[j] += 16.0 * np.sum(base * np.sin(np.pi * (FX * u[0] + FY * u[1])) ** 2)
+    return out

@@ -372,6 +372,71 @@ ORACLE_API void oracle_diff_piston_sf(int64_t K, const double* fx, const double*
 }
 
 /* ------------------------------------------------------------------ */
+/* Temporal differential-piston structure function (Sec. 4.4, the      */
+/* statistical test of the worked example)                              */
+/* ------------------------------------------------------------------ */
+/* Frozen flow (Taylor): the turbulence moves with velocity v, so at time
+ * t the telescope at c sees the screen at c - v t.  pist[r][0][m] and
+ * pist[r][1][m] are the pistons of telescopes 1 and 2 at t_m = m dt.  For
+ * each realisation the structure function of the differential piston
+ * dp(t) = p1(t) - p2(t) at lag j dt is the average over the M - j
+ * available pairs of (dp(t_m + j dt) - dp(t_m))^2; sf[j] averages it over
+ * the R realisations and sf_stderr[j] is the standard error of that mean
+ * (sample standard deviation over realisations / sqrt R).  sf[0] = 0. */
+ORACLE_API void oracle_temporal_sf(const double* pist, int64_t R, int64_t M, double* sf,
+                                   double* sf_stderr) {
+    for (int64_t j = 0; j < M; ++j) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int64_t r = 0; r < R; ++r) {
+            const double* p1 = pist + r * 2 * M;
+            const double* p2 = p1 + M;
+            double acc = 0.0;
+            for (int64_t m = 0; m + j < M; ++m) {
+                double d = (p1[m + j] - p2[m + j]) - (p1[m] - p2[m]);
+                acc += d * d;
+            }
+            double v = acc / (double)(M - j);
+            s1 += v;
+            s2 += v * v;
+        }
+        sf[j] = s1 / (double)R;
+        if (sf_stderr) {
+            double var = R > 1 ? (s2 - s1 * s1 / (double)R) / (double)(R - 1) : 0.0;
+            sf_stderr[j] = sqrt(var > 0.0 ? var / (double)R : 0.0);
+        }
+    }
+}
+
+/* The whole experiment: aperture centres c - v t_m of both telescopes
+ * (t_m = m dt), pistons by Eq. 3 with the aperture-filtered weights w (the
+ * filter of equal apertures folds into the weight, Eq. 7), then the
+ * temporal structure function above. */
+ORACLE_API void oracle_temporal_experiment(int64_t K, const double* fx, const double* fy,
+                                           const double* w, const double* c1, const double* c2,
+                                           const double* v, double dt, int64_t M, int64_t R,
+                                           int64_t R_block, uint64_t seed, uint64_t counter,
+                                           int32_t mode, double* sf, double* sf_stderr) {
+    int64_t P = 2 * M;
+    double* px = (double*)malloc(sizeof(double) * (size_t)P);
+    double* py = (double*)malloc(sizeof(double) * (size_t)P);
+    for (int64_t m = 0; m < M; ++m) {
+        double t = (double)m * dt;
+        px[m] = c1[0] - v[0] * t;
+        py[m] = c1[1] - v[1] * t;
+        px[M + m] = c2[0] - v[0] * t;
+        py[M + m] = c2[1] - v[1] * t;
+    }
+    double* pist = (double*)malloc(sizeof(double) * (size_t)(R * P));
+    int64_t n_sets = (R + R_block - 1) / R_block;
+    direct_sum(K, fx, fy, w, P, px, py, NULL, n_sets, R, R_block, seed, counter, mode, NULL,
+               pist);
+    oracle_temporal_sf(pist, R, M, sf, sf_stderr);
+    free(pist);
+    free(px);
+    free(py);
+}
+
+/* ------------------------------------------------------------------ */
 /* Learned proposal density (the paper suggests systematising the      */
 /* sampling with a mapping that knows the PSD, Sec. 5; the model below */
 /* is this project's definition of such a mapping)                     */
