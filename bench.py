@@ -68,7 +68,8 @@ def parse():
                     help="target duration of the oracle sample (0 disables it)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain-vs-chosen comparison (learned proposal)")
-    ap.add_argument("--workload", choices=["diffpiston", "phase", "large_screen", "batched"],
+    ap.add_argument("--workload", choices=["diffpiston", "phase", "large_screen", "batched",
+                                           "temporal"],
                     default="diffpiston",
                     help="diffpiston: the headline line; the others print their own report")
     return ap.parse_args()
@@ -345,6 +346,50 @@ def workload_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def workload_temporal(args):
+    """The statistical test of the worked example (Sec. 4.4, Fig. 5): two
+    UTs (D = 8 m, d = 1.1 m) 56.5 m apart, frozen flow at 10.2 m/s along the
+    baseline, L0 = 22 m, r0 = 0.1 m at 0.5 um, Cartesian R2 with
+    df = 0.25/22 and fmax = 0.25 (N = 44, K = 1936) drawn afresh for every
+    realisation (R_block = 1), 2000 realisations, 1024 samples 1 ms apart;
+    the temporal structure function of the differential piston in FP64,
+    FP32 and BF16x6 against the exact expectation over the sampling square
+    and the untruncated analytic curve, as OPD (lambda / 2 pi)^2 D in um^2."""
+    import numpy as np
+    import torch
+    import paper_2404_02978_amd as q
+    from oracle import analytic as A
+    N, df = 44, 0.25 / 22
+    K, R, M, dt = N * N, 2000, 1024, 1e-3
+    D, d, L0, r0, lam = 8.0, 1.1, 22.0, 0.1, 0.5e-6
+    B, v = np.array([56.5, 0.0]), np.array([10.2, 0.0])
+    ctx = q.Context(0)
+    opd = (lam / (2 * np.pi)) ** 2 * 1e12  # rad^2 -> um^2
+    lags = np.array([1, 2, 5, 10, 20, 50, 100, 200, 500, 1000, 1023])
+    ex = A.temporal_sf_square(lags * dt, B, v, r0, L0, D, d, half_width=0.25, n=200)
+    iso = A.temporal_sf(lags * dt, B, v, r0, L0, D, d)
+    out = {"workload": "frozen-flow differential piston, UTs 56.5 m apart, 10.2 m/s, L0=22 m, "
+                       "Cartesian R2 N=44 (K=1936), R_block=1, R=2000, 1024 samples at 1 ms",
+           "terms": float(R) * K * 2 * M, "lags_ms": (lags * dt * 1e3).tolist(),
+           "expected_opd_um2_square": (ex * opd).tolist(),
+           "analytic_opd_um2_untruncated": (iso * opd).tolist(), "runs": {}}
+    for name, prec in (("fp64", q.PREC_FP64), ("fp32", q.PREC_FP32), ("bf16x6", q.PREC_BF16X6)):
+        holder = {}
+
+        def call():
+            s = q.cartesian_sampler(N, df)
+            holder["r"] = ctx.temporal_piston_structure(
+                q.psd(r0, L0), q.Aperture(D, d), (0.0, 0.0), tuple(-B), tuple(v), dt, M, s, K, R,
+                1, rng=q.Rng(0, 0, 0), precision=prec)
+        ms = _time_call(call, reps=3)
+        sf, se = (t.cpu().numpy() for t in holder["r"])
+        out["runs"][name] = {"ms": ms, "realisations_per_s": R / (ms * 1e-3),
+                             "terms_per_s": R * K * 2 * M / (ms * 1e-3),
+                             "opd_um2": (sf[lags] * opd).tolist(),
+                             "z_vs_expected": ((sf[lags] - ex) / se[lags]).round(2).tolist()}
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration():
     """A plain 1 GiB device copy: FETCH_SIZE / WRITE_SIZE of this dispatch
     calibrate the HBM byte counters against a known traffic."""
@@ -365,7 +410,7 @@ def main():
         return
     if args.workload != "diffpiston":
         {"phase": workload_phase, "large_screen": workload_large_screen,
-         "batched": workload_batched}[args.workload](args)
+         "batched": workload_batched, "temporal": workload_temporal}[args.workload](args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "

@@ -279,6 +279,38 @@ QRFS_API qrfs_status qrfs_diff_piston_structure_sets(qrfs_context* ctx, int64_t 
                                                      double* sf, double* sf_stderr,
                                                      void* stream);
 
+/* ----------------------------------------------- frozen-flow time series */
+/* Temporal structure function of the differential piston (the statistical
+ * test of Sec. 4.4): pistons [R][2][M] hold, per realisation, the pistons of
+ * telescopes 1 and 2 at times t_m = m dt (double for QRFS_PREC_FP64, float
+ * otherwise; device).  For lag j, each realisation contributes the mean over
+ * its M - j pairs of (dp(t_m + j dt) - dp(t_m))^2, dp = p1 - p2; sf[j] is
+ * the mean over realisations, sf_stderr[j] its standard error (sample
+ * standard deviation / sqrt R; NULL to skip), both double[M] (device,
+ * rad^2; sf[0] = 0).  Accumulated in FP64, reduced in a fixed order.
+ * Errors: R < 1; M outside [1, 4096]; NULL or misaligned arrays; unknown
+ * precision. */
+QRFS_API qrfs_status qrfs_temporal_sf(qrfs_context* ctx, int64_t R, int64_t M, int32_t precision,
+                                      const void* pistons, double* sf, double* sf_stderr,
+                                      void* stream);
+
+/* The experiment of Sec. 4.4 end to end under frozen flow (Taylor): the
+ * turbulence moves with velocity v (m/s), so at time t the telescope at c
+ * sees the screen at c - v t.  Draws ceil(R/R_block) frequency sets of K
+ * points with the sampler (advancing s->index by n_sets*K), weights them
+ * with the PSD and the filter of the equal apertures ap (Eq. 7), evaluates
+ * the pistons of Eq. 3 at c1 - v t_m and c2 - v t_m (t_m = m dt, m < M) for
+ * R realisations (coefficients from rng) and returns the temporal structure
+ * function of qrfs_temporal_sf.  c1, c2, v: host double[2] (m, m/s).
+ * The pistons equal qrfs_synthesize_phase with the filtered weights at
+ * those 2M points.  Errors: as qrfs_diff_piston_structure (ap required),
+ * M outside [1, 4096], dt negative or not finite, NULL c1/c2/v. */
+QRFS_API qrfs_status qrfs_temporal_piston_structure(
+    qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aperture* ap, const double* c1,
+    const double* c2, const double* v, double dt, int64_t M, qrfs_sampler* s, int64_t K,
+    int64_t R, int64_t R_block, const qrfs_rng* rng, int32_t precision, double* sf,
+    double* sf_stderr, void* stream);
+
 /* ------------------------------------------------------ learned proposal */
 /* A proposal density for the frequency sampler, learned from the variance
  * contributions the plain method generates (the paper leaves the choice of

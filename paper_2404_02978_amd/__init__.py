@@ -136,6 +136,12 @@ def load_library():
         "qrfs_diff_piston_structure": (S, [_P, ctypes.POINTER(Psd), ctypes.POINTER(Aperture), _I64,
                                            _P, _P, ctypes.POINTER(Sampler), _I64, _I64, _I64,
                                            ctypes.POINTER(Rng), _I32, _P, _P, _P]),
+        "qrfs_temporal_sf": (S, [_P, _I64, _I64, _I32, _P, _P, _P, _P]),
+        "qrfs_temporal_piston_structure": (
+            S, [_P, ctypes.POINTER(Psd), ctypes.POINTER(Aperture), ctypes.POINTER(ctypes.c_double),
+                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                _I64, ctypes.POINTER(Sampler), _I64, _I64, _I64, ctypes.POINTER(Rng), _I32, _P, _P,
+                _P]),
     }
     _D = ctypes.c_double
     sig.update({
@@ -317,6 +323,38 @@ class Context:
             self._h, ctypes.byref(psd_), ctypes.byref(aperture), nB, _dev_f64(bx, "bx"),
             _dev_f64(by, "by", nB), ctypes.byref(sampler), K, R, R_block, ctypes.byref(rng),
             precision, _ptr(sf), _ptr(se), _stream()))
+        return sf, se
+
+    def temporal_sf(self, pistons, with_stderr=True):
+        """Time-lag structure function of the differential piston (Sec. 4.4)
+        from pistons [R][2][M] (float64 -> FP64 path, float32 otherwise).
+        Returns (sf, stderr) float64 [M] on the device."""
+        if not isinstance(pistons, torch.Tensor) or not pistons.is_cuda or pistons.dim() != 3 \
+                or pistons.shape[1] != 2 or not pistons.is_contiguous():
+            raise TypeError("pistons must be a contiguous CUDA tensor [R][2][M]")
+        if pistons.dtype not in (torch.float64, torch.float32):
+            raise TypeError("pistons must be float64 or float32")
+        R, _, M = pistons.shape
+        prec = PREC_FP64 if pistons.dtype == torch.float64 else PREC_FP32
+        sf = torch.empty(M, dtype=torch.float64, device=self.device)
+        se = torch.empty_like(sf) if with_stderr else None
+        _check(load_library().qrfs_temporal_sf(self._h, R, M, prec, _ptr(pistons), _ptr(sf),
+                                               _ptr(se), _stream()))
+        return sf, se
+
+    def temporal_piston_structure(self, psd_, aperture, c1, c2, v, dt, M, sampler, K, R,
+                                  R_block, rng=None, precision=PREC_FP32, with_stderr=True):
+        """The frozen-flow experiment of Sec. 4.4 end to end: telescopes at
+        c1, c2 (m), wind v (m/s), M samples dt apart.  Returns (sf, stderr)
+        float64 [M] (rad^2) on the device; advances sampler.index."""
+        D2 = ctypes.c_double * 2
+        sf = torch.empty(M, dtype=torch.float64, device=self.device)
+        se = torch.empty_like(sf) if with_stderr else None
+        rng = rng if rng is not None else Rng(0, 0, COEF_GAUSS_CS)
+        _check(load_library().qrfs_temporal_piston_structure(
+            self._h, ctypes.byref(psd_), ctypes.byref(aperture), D2(*c1), D2(*c2), D2(*v),
+            float(dt), M, ctypes.byref(sampler), K, R, R_block, ctypes.byref(rng), precision,
+            _ptr(sf), _ptr(se), _stream()))
         return sf, se
 
     def diff_piston_structure_sets(self, K, fx, fy, w, bx, by, R, R_block, rng=None,

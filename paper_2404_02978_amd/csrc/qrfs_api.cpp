@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <string>
 
 #include "qrfs.h"
@@ -558,6 +559,145 @@ qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
     }
     hipError_t e = qrfs::launch_reduce_sf(partial, plan.n_partial_tiles, nB, R, sf, sf_stderr,
                                           stream_);
+    if (e != hipSuccess) return hip_fail(e, "reduction launch");
+    s->index += (uint64_t)(n_sets * K);
+    return ok();
+}
+
+qrfs_status qrfs_temporal_sf(qrfs_context* ctx, int64_t R, int64_t M, int32_t precision,
+                             const void* pistons, double* sf, double* sf_stderr, void* stream) {
+    if (R < 1) return fail(QRFS_ERR_INVALID_ARG, "R must be >= 1 (got %lld)", (long long)R);
+    if (M < 1 || M > qrfs::TEMPORAL_MAX_M)
+        return fail(QRFS_ERR_INVALID_ARG, "M must be in [1, %d] (got %lld)", qrfs::TEMPORAL_MAX_M,
+                    (long long)M);
+    if (precision != QRFS_PREC_FP64 && precision != QRFS_PREC_FP32 &&
+        precision != QRFS_PREC_SPLIT_BF16 && precision != QRFS_PREC_BF16X6)
+        return fail(QRFS_ERR_INVALID_ARG, "unknown precision %d", precision);
+    if (!pistons) return fail(QRFS_ERR_INVALID_ARG, "pistons is NULL");
+    if (((uintptr_t)pistons & (precision == QRFS_PREC_FP64 ? 7u : 3u)) != 0)
+        return fail(QRFS_ERR_INVALID_ARG, "pistons is misaligned");
+    CHECK_PTR(sf);
+    if (sf_stderr && !aligned8(sf_stderr))
+        return fail(QRFS_ERR_INVALID_ARG, "sf_stderr is not 8-byte aligned");
+    if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
+    const int64_t nb = qrfs::temporal_blocks(R);
+    qrfs_status st = ensure_workspace(ctx, align256((size_t)nb * M * 2 * sizeof(double)));
+    if (st) return st;
+    double* part = (double*)ctx->ws;
+    hipStream_t stream_ = (hipStream_t)stream;
+    hipError_t e = qrfs::launch_temporal_rows(precision == QRFS_PREC_FP64, pistons, R, M, part,
+                                              stream_);
+    if (e != hipSuccess) return hip_fail(e, "temporal estimator launch");
+    e = qrfs::launch_reduce_sf(part, nb, M, R, sf, sf_stderr, stream_);
+    if (e != hipSuccess) return hip_fail(e, "reduction launch");
+    return ok();
+}
+
+qrfs_status qrfs_temporal_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
+                                           const qrfs_aperture* ap, const double* c1,
+                                           const double* c2, const double* v, double dt,
+                                           int64_t M, qrfs_sampler* s, int64_t K, int64_t R,
+                                           int64_t R_block, const qrfs_rng* rng,
+                                           int32_t precision, double* sf, double* sf_stderr,
+                                           void* stream) {
+    qrfs_status st = check_psd(psd);
+    if (st) return st;
+    if (!ap) return fail(QRFS_ERR_INVALID_ARG, "aperture is required");
+    if ((st = check_ap(ap))) return st;
+    if ((st = check_sampler(s))) return st;
+    if (M < 1 || M > qrfs::TEMPORAL_MAX_M)
+        return fail(QRFS_ERR_INVALID_ARG, "M must be in [1, %d] (got %lld)", qrfs::TEMPORAL_MAX_M,
+                    (long long)M);
+    if ((st = check_sum_common(K, 2 * M, R, R_block, rng, nullptr, precision))) return st;
+    if (!c1 || !c2 || !v) return fail(QRFS_ERR_INVALID_ARG, "c1, c2 and v are required");
+    if (!(dt >= 0.0) || !std::isfinite(dt))
+        return fail(QRFS_ERR_INVALID_ARG, "dt must be finite and >= 0");
+    for (int i = 0; i < 2; ++i)
+        if (!std::isfinite(c1[i]) || !std::isfinite(c2[i]) || !std::isfinite(v[i]))
+            return fail(QRFS_ERR_INVALID_ARG, "c1, c2, v must be finite");
+    CHECK_PTR(sf);
+    if (sf_stderr && !aligned8(sf_stderr))
+        return fail(QRFS_ERR_INVALID_ARG, "sf_stderr is not 8-byte aligned");
+    if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
+
+    const int64_t n_sets = cdiv(R, R_block);
+    const int64_t P = 2 * M;
+    const bool fp64 = precision == QRFS_PREC_FP64;
+    const size_t esize = fp64 ? sizeof(double) : sizeof(float);
+    // pieces of whole sets (at most ~1 GiB of frequencies and pistons) whose
+    // first realisation is a multiple of the estimator's row blocks, so the
+    // fixed-order reduction sees the same blocks however the sets are cut
+    const int64_t q = qrfs::TEMPORAL_ROWS_PER_BLOCK / std::gcd(R_block,
+                                                              (int64_t)qrfs::TEMPORAL_ROWS_PER_BLOCK);
+    const size_t per_set = (size_t)K * 4 * sizeof(double) + (size_t)R_block * P * esize;
+    int64_t spb = (int64_t)(((size_t)1 << 30) / per_set);
+    spb = spb / q * q;
+    if (spb < q) spb = q;
+    if (spb > n_sets) spb = n_sets;
+    const int64_t nb = qrfs::temporal_blocks(R);
+    const size_t part_bytes = align256((size_t)nb * M * 2 * sizeof(double));
+    const size_t pt_bytes = align256((size_t)P * sizeof(double));
+    const size_t arr = align256((size_t)spb * K * sizeof(double));
+    const size_t pist_bytes = align256((size_t)spb * R_block * P * esize);
+    if ((st = ensure_workspace(ctx, part_bytes + 2 * pt_bytes + 4 * arr + pist_bytes))) return st;
+    char* base = (char*)ctx->ws;
+    double* part = (double*)base;
+    double* px = (double*)(base + part_bytes);
+    double* py = (double*)(base + part_bytes + pt_bytes);
+    char* fbase = base + part_bytes + 2 * pt_bytes;
+    double* fx = (double*)fbase;
+    double* fy = (double*)(fbase + arr);
+    double* area = (double*)(fbase + 2 * arr);
+    double* w = (double*)(fbase + 3 * arr);
+    void* pist = fbase + 4 * arr;
+    hipStream_t stream_ = (hipStream_t)stream;
+    const double c = psd->c > 0.0 ? psd->c : qrfs::kPsdConstant;
+
+    hipError_t e = qrfs::launch_taylor_points(c1, c2, v, dt, M, px, py, stream_);
+    if (e != hipSuccess) return hip_fail(e, "point launch");
+    for (int64_t s0 = 0; s0 < n_sets; s0 += spb) {
+        const int64_t s1 = s0 + spb < n_sets ? s0 + spb : n_sets;
+        const int64_t ns = s1 - s0;
+        const int64_t r0 = s0 * R_block;
+        const int64_t rows = (s1 * R_block < R ? s1 * R_block : R) - r0;
+        e = sample_any(s, s->index + (uint64_t)(s0 * K), ns, K, fx, fy, area, stream_);
+        if (e != hipSuccess) return hip_fail(e, "sampler launch");
+        // equal apertures: the filter of Eq. 7 folds into the weight
+        e = qrfs::launch_weights(psd->model, c, psd->r0, psd->L0, 1, ap->D, ap->d, ns * K, fx, fy,
+                                 area, w, stream_);
+        if (e != hipSuccess) return hip_fail(e, "weights launch");
+        // the piece as a problem of its own: realisations r0 .. r0 + rows
+        qrfs::SumArgs a{};
+        a.K = K;
+        a.fx = fx;
+        a.fy = fy;
+        a.w = w;
+        a.P = P;
+        a.px = px;
+        a.py = py;
+        a.R = rows;
+        a.R_block = R_block;
+        a.seed = rng->seed;
+        a.counter = rng->counter + (uint64_t)r0;
+        a.mode = rng->mode;
+        a.coef = nullptr;
+        a.out = pist;
+        a.partial = nullptr;
+        a.ksplit = 1;
+        a.kspan = K;
+        a.phi_part = nullptr;
+        if ((st = run_sum(precision, qrfs::BASIS_PHASE, qrfs::EPI_STORE, a, ns, stream_)))
+            return st;
+        e = qrfs::launch_temporal_rows(fp64, pist, rows, M,
+                                       part + (r0 / qrfs::TEMPORAL_ROWS_PER_BLOCK) * M * 2,
+                                       stream_);
+        if (e != hipSuccess) return hip_fail(e, "temporal estimator launch");
+    }
+    e = qrfs::launch_reduce_sf(part, nb, M, R, sf, sf_stderr, stream_);
     if (e != hipSuccess) return hip_fail(e, "reduction launch");
     s->index += (uint64_t)(n_sets * K);
     return ok();

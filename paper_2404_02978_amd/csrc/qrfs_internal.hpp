@@ -137,6 +137,18 @@ hipError_t launch_weights(int model, double c, double r0, double L0, int has_ap,
                           double d, int64_t n, const double* fx, const double* fy,
                           const double* area, double* w, hipStream_t st);
 
+// Frozen-flow temporal structure function (time series of M <= 4096 points).
+constexpr int TEMPORAL_MAX_M = 4096;
+constexpr int TEMPORAL_ROWS_PER_BLOCK = 8;
+// points c1 - v m dt (m < M), then c2 - v m dt
+hipError_t launch_taylor_points(const double c1[2], const double c2[2], const double v[2],
+                                double dt, int64_t M, double* px, double* py, hipStream_t st);
+// blocks of TEMPORAL_ROWS_PER_BLOCK realisations that launch_temporal_rows uses
+int64_t temporal_blocks(int64_t R);
+// pist [R][2][M] (double when fp64, else float) -> part[temporal_blocks(R)][M][2]
+hipError_t launch_temporal_rows(bool fp64, const void* pist, int64_t R, int64_t M, double* part,
+                                hipStream_t st);
+
 // sf[p] = S2/R, stderr[p] from partial[n_tiles][P][2] in a fixed order.
 hipError_t launch_reduce_sf(const double* partial, int64_t n_tiles, int64_t P, int64_t R,
                             double* sf, double* sf_stderr, hipStream_t st);
