@@ -54,6 +54,9 @@ def _load():
         "oracle_diff_piston_sf": (None, [_i64, _p, _p, _p, _i64, _p, _p, _i64, _i64, _u64,
                                          _u64, _i32, _p, _p]),
         "oracle_temporal_sf": (None, [_p, _i64, _i64, _p, _p]),
+        "oracle_concentric_map": (None, [_d, _d, _p, _p]),
+        "oracle_sample_disc": (None, [_u64, _u64, _u64, _i64, _i64, _d, _p, _p, _p]),
+        "oracle_choose_cartesian": (_i64, [_i32, _d, _d, _d, _i32, _d, _d, _d, _d, _p]),
         "oracle_temporal_experiment": (None, [_i64, _p, _p, _p, _p, _p, _p, _d, _i64, _i64,
                                               _i64, _u64, _u64, _i32, _p, _p]),
     }
@@ -125,6 +128,30 @@ def sample_logpolar(n_sets, K, fmin, fmax, index=0, s0x=SEED_HALF, s0y=SEED_HALF
     _load().oracle_sample_logpolar(s0x, s0y, index, n_sets, K, fmin, fmax, _ptr(fx), _ptr(fy),
                                    _ptr(area))
     return fx, fy, area
+
+
+def concentric_map(ux, uy):
+    """Square-to-disc map of one point (ux, uy) in [0,1)^2 -> (x, y), |(x, y)| < 1."""
+    x, y = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _load().oracle_concentric_map(float(ux), float(uy), ctypes.byref(x), ctypes.byref(y))
+    return x.value, y.value
+
+
+def sample_disc(n_sets, K, fmax, index=0, s0x=SEED_HALF, s0y=SEED_HALF):
+    """Polar quasi-random frequencies on the disc |f| < fmax (Sec. 3.2)."""
+    n = n_sets * K
+    fx, fy, area = np.zeros(n), np.zeros(n), np.zeros(n)
+    _load().oracle_sample_disc(s0x, s0y, index, n_sets, K, fmax, _ptr(fx), _ptr(fy), _ptr(area))
+    return fx, fy, area
+
+
+def choose_cartesian(df, eps, r0=0.1, L0=25.0, D=None, d=0.0, c=None, model=PSD_VON_KARMAN):
+    """Stopping rule for N (Sec. 4.3): returns (N, sigma^2) with N df = 2 max f."""
+    c = psd_constant() if c is None else c
+    s2 = ctypes.c_double(0.0)
+    N = _load().oracle_choose_cartesian(model, c, r0, L0, 0 if D is None else 1,
+                                        0.0 if D is None else D, d, df, eps, ctypes.byref(s2))
+    return int(N), s2.value
 
 
 def psd_constant():

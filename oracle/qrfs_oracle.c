@@ -135,6 +135,48 @@ ORACLE_API void oracle_sample_logpolar(uint64_t s0x, uint64_t s0y, uint64_t inde
     free(uy);
 }
 
+/* Square-to-disc map for polar quasi-random frequencies (Sec. 3.2 cites
+ * Shirley and Chiu's concentric map): (ux, uy) in [0,1)^2 -> (a, b) =
+ * (2ux - 1, 2uy - 1); the concentric square max(|a|, |b|) = rho goes to the
+ * circle of radius rho, the position along the square's edge to the angle
+ * linearly, so the map preserves area (Jacobian pi/4 everywhere). */
+ORACLE_API void oracle_concentric_map(double ux, double uy, double* x, double* y) {
+    double a = 2.0 * ux - 1.0, b = 2.0 * uy - 1.0;
+    double r, phi;
+    if (a == 0.0 && b == 0.0) {
+        r = 0.0;
+        phi = 0.0;
+    } else if (fabs(a) > fabs(b)) {
+        r = a;
+        phi = (M_PI / 4.0) * (b / a);
+    } else {
+        r = b;
+        phi = M_PI / 2.0 - (M_PI / 4.0) * (a / b);
+    }
+    *x = r * cos(phi);
+    *y = r * sin(phi);
+}
+
+/* Polar quasi-random frequencies: R2 points through the concentric map onto
+ * the disc |f| < fmax; every point stands for the same cell area
+ * pi fmax^2 / K. */
+ORACLE_API void oracle_sample_disc(uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n_sets,
+                                   int64_t K, double fmax, double* fx, double* fy, double* area) {
+    int64_t n = n_sets * K;
+    double* ux = (double*)malloc(sizeof(double) * (size_t)n);
+    double* uy = (double*)malloc(sizeof(double) * (size_t)n);
+    oracle_r2_points(s0x, s0y, index, n, ux, uy);
+    for (int64_t i = 0; i < n; ++i) {
+        double x, y;
+        oracle_concentric_map(ux[i], uy[i], &x, &y);
+        fx[i] = fmax * x;
+        fy[i] = fmax * y;
+        area[i] = M_PI * fmax * fmax / (double)K;
+    }
+    free(ux);
+    free(uy);
+}
+
 /* ------------------------------------------------------------------ */
 /* Phase PSD and aperture filter, Sec. 4.1 Eq. 7                       */
 /* ------------------------------------------------------------------ */
@@ -369,6 +411,59 @@ ORACLE_API void oracle_diff_piston_sf(int64_t K, const double* fx, const double*
     free(pist);
     free(px);
     free(py);
+}
+
+/* ------------------------------------------------------------------ */
+/* Hyper-parameters of the Cartesian sampling (Sec. 4.3)                */
+/* ------------------------------------------------------------------ */
+/* g(x) = int_0^x f W(f) F(f)^2 df (the radial integral of the filtered
+ * PSD; F = 1 without aperture) and its increments over steps of df,
+ * inc(n) = g(n df) - g((n-1) df), by composite Simpson with 64 panels per
+ * step.  Stopping rule: the increments must stay below eps g(inf) from
+ * the step after n* on (eps relative to the saturated variance, the
+ * paper's eps << sigma^2); max f = n* df, so N = 2 n* (N df = 2 max f).
+ * g(inf) is the sum of the increments up to x_max = 200/D with an
+ * aperture, 2000/L0 without (the integrand decays faster than f^-5 and as
+ * f^-8/3: the tails left out are below 1e-7 and 3e-6 of g(inf)).
+ * Returns N, or 0 for the Kolmogorov model (g diverges at f = 0). */
+static double filtered_radial(int32_t model, double c, double r0, double L0, int32_t has_ap,
+                              double D, double d, double f) {
+    if (f <= 0.0) return 0.0;
+    double w = oracle_psd(model, c, r0, L0, f);
+    double F = has_ap ? oracle_aperture_filter(D, d, f) : 1.0;
+    return f * w * F * F;
+}
+
+ORACLE_API int64_t oracle_choose_cartesian(int32_t model, double c, double r0, double L0,
+                                           int32_t has_ap, double D, double d, double df,
+                                           double eps, double* sigma2) {
+    if (model != 1) return 0;
+    double x_max = has_ap ? 200.0 / D : 2000.0 / L0;
+    int64_t n_max = (int64_t)ceil(x_max / df);
+    double* inc = (double*)malloc(sizeof(double) * (size_t)n_max);
+    double total = 0.0;
+    const int panels = 64;
+    for (int64_t n = 1; n <= n_max; ++n) {
+        double a = (double)(n - 1) * df, h = df / panels, acc = 0.0;
+        for (int p = 0; p < panels; ++p) {
+            double x0 = a + p * h;
+            acc += h / 6.0 *
+                   (filtered_radial(model, c, r0, L0, has_ap, D, d, x0) +
+                    4.0 * filtered_radial(model, c, r0, L0, has_ap, D, d, x0 + 0.5 * h) +
+                    filtered_radial(model, c, r0, L0, has_ap, D, d, x0 + h));
+        }
+        inc[n - 1] = acc;
+        total += acc;
+    }
+    int64_t nstar = 1;
+    for (int64_t n = n_max; n >= 1; --n)
+        if (inc[n - 1] >= eps * total) {
+            nstar = n;
+            break;
+        }
+    free(inc);
+    if (sigma2) *sigma2 = 2.0 * M_PI * total;
+    return 2 * nstar;
 }
 
 /* ------------------------------------------------------------------ */
