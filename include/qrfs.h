@@ -134,6 +134,11 @@ typedef struct {
  *       N df = 2 max|f|, as the worked example of Sec. 4.4 fixes.
  *   R2_LOGPOLAR: |f| = fmin (fmax/fmin)^(u_x), angle = 2 pi u_y,
  *       cell area = 2 pi ln(fmax/fmin) |f|^2 / K.
+ *   R2_DISC: polar quasi-random frequencies (Sec. 3.2's square-to-disc
+ *       mapping): the concentric map of Shirley and Chiu sends
+ *       (a, b) = (2u_x - 1, 2u_y - 1) to radius max(|a|, |b|) fmax and an
+ *       angle linear along the concentric square's edge; it preserves area,
+ *       so every point stands for pi fmax^2 / K.  Uses fmax only.
  *   LEARNED: the points are drawn from the sampling table of `proposal`
  *       (built by qrfs_proposal_tabulate): u_x through the inverse CDF of
  *       its piecewise-constant density in ln|f| over [fmin, fmax] of the
@@ -146,12 +151,13 @@ typedef struct {
 #define QRFS_SAMPLER_R2_CARTESIAN 0
 #define QRFS_SAMPLER_R2_LOGPOLAR 1
 #define QRFS_SAMPLER_LEARNED 2
+#define QRFS_SAMPLER_R2_DISC 3
 typedef struct {
     int32_t scheme;
     int32_t N;   /* Cartesian: points per axis of the domain (> 0)   */
     double df;   /* Cartesian: frequency pitch (> 0)                 */
     double fmin; /* log-polar: band, 0 < fmin < fmax                 */
-    double fmax;
+    double fmax; /* log-polar: upper band edge; disc: radius (> 0)   */
     uint64_t seed_x;
     uint64_t seed_y;
     uint64_t index;
@@ -209,6 +215,21 @@ QRFS_API qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s,
 QRFS_API qrfs_status qrfs_weights(qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aperture* ap,
                          int64_t n, const double* fx, const double* fy, const double* area,
                          double* w, void* stream);
+
+/* Hyper-parameters of the Cartesian sampler (Sec. 4.3), host-only (no
+ * device work, no context): with g(x) = int_0^x f W(f) F(f)^2 df (F the
+ * filter of ap, 1 when ap is NULL), the smallest max|f| = n* df beyond which
+ * every increment g(n df) - g((n-1) df) stays below eps g(inf) (eps
+ * relative to the saturated variance, the paper's eps << sigma^2); returns
+ * *N = 2 n* (N df = 2 max|f|), *df_out the pitch used (df <= 0 selects the
+ * paper's 0.25 / L0) and, when sigma2 is not NULL, the variance
+ * 2 pi g(inf) (rad^2, of the piston when ap is given).
+ * Errors: Kolmogorov model (g diverges at f = 0: QRFS_ERR_UNSUPPORTED);
+ * r0, L0 <= 0; eps outside (0, 1); bad aperture; NULL N or df_out;
+ * more than 2^31 steps. */
+QRFS_API qrfs_status qrfs_choose_cartesian(const qrfs_psd* psd, const qrfs_aperture* ap,
+                                           double df, double eps, int32_t* N, double* df_out,
+                                           double* sigma2);
 
 /* Phase field, Eq. 3: phase[r][p] = phi_r(px[p], py[p]) for r < R, p < P.
  * fx, fy, w: double[n_sets][K] (n_sets = ceil(R/R_block)); px, py:

@@ -27,6 +27,7 @@ PSD_VON_KARMAN = 1
 SAMPLER_R2_CARTESIAN = 0
 SAMPLER_R2_LOGPOLAR = 1
 SAMPLER_LEARNED = 2
+SAMPLER_R2_DISC = 3
 COEF_GAUSS_CS = 0
 COEF_EQ3 = 1
 PREC_FP64 = 0
@@ -79,6 +80,23 @@ def logpolar_sampler(fmin, fmax, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
     return Sampler(SAMPLER_R2_LOGPOLAR, 0, 0.0, fmin, fmax, seed_x, seed_y, index, None)
 
 
+def disc_sampler(fmax, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
+    """Polar quasi-random frequencies on the disc |f| < fmax (Sec. 3.2)."""
+    return Sampler(SAMPLER_R2_DISC, 0, 0.0, 0.0, fmax, seed_x, seed_y, index, None)
+
+
+def choose_cartesian(psd_, aperture=None, df=0.0, eps=1e-4):
+    """Cartesian hyper-parameters by the stopping rule of Sec. 4.3 (host
+    only): returns (N, df, sigma2)."""
+    N = _I32(0)
+    dfo = ctypes.c_double(0.0)
+    s2 = ctypes.c_double(0.0)
+    _check(load_library().qrfs_choose_cartesian(
+        ctypes.byref(psd_), None if aperture is None else ctypes.byref(aperture), float(df),
+        float(eps), ctypes.byref(N), ctypes.byref(dfo), ctypes.byref(s2)))
+    return N.value, dfo.value, s2.value
+
+
 def cartesian_sampler(N, df, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
     return Sampler(SAMPLER_R2_CARTESIAN, N, df, 0.0, 0.0, seed_x, seed_y, index, None)
 
@@ -122,6 +140,10 @@ def load_library():
         "qrfs_context_create": (S, [ctypes.POINTER(_P), _I32]),
         "qrfs_context_destroy": (S, [_P]),
         "qrfs_context_set_tuning": (S, [_P, _I32, _I64]),
+        "qrfs_choose_cartesian": (S, [ctypes.POINTER(Psd), ctypes.POINTER(Aperture), ctypes.c_double,
+                                      ctypes.c_double, ctypes.POINTER(_I32),
+                                      ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]),
         "qrfs_sample_frequencies": (S, [_P, ctypes.POINTER(Sampler), _I64, _I64, _P, _P, _P, _P]),
         "qrfs_weights": (S, [_P, ctypes.POINTER(Psd), ctypes.POINTER(Aperture), _I64, _P, _P, _P,
                              _P, _P]),

@@ -123,6 +123,9 @@ qrfs_status check_sampler(const qrfs_sampler* s) {
         if (!(s->fmin > 0.0) || !(s->fmax > s->fmin) || !std::isfinite(s->fmax))
             return fail(QRFS_ERR_INVALID_ARG, "log-polar band needs 0 < fmin < fmax (got %g, %g)",
                         s->fmin, s->fmax);
+    } else if (s->scheme == QRFS_SAMPLER_R2_DISC) {
+        if (!(s->fmax > 0.0) || !std::isfinite(s->fmax))
+            return fail(QRFS_ERR_INVALID_ARG, "disc radius fmax must be > 0 (got %g)", s->fmax);
     } else {
         return fail(QRFS_ERR_INVALID_ARG, "unknown sampler scheme %d", s->scheme);
     }

@@ -95,6 +95,9 @@ qrfs_status check_instance(const qrfs_batch_instance& in, int64_t i) {
         if (!(s.fmin > 0.0) || !(s.fmax > s.fmin))
             return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: needs 0 < fmin < fmax",
                             (long long)i);
+    } else if (s.scheme == QRFS_SAMPLER_R2_DISC) {
+        if (!(s.fmax > 0.0))
+            return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: needs fmax > 0", (long long)i);
     } else {
         return api_fail(QRFS_ERR_UNSUPPORTED, "instance %lld: sampler scheme %d not accepted",
                         (long long)i, s.scheme);

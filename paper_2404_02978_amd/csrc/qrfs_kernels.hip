@@ -11,7 +11,8 @@ namespace qrfs {
 
 // ------------------------------------------------------------- sampler ----
 // One thread per frequency.  Point n = index + 1 + i of the R2 sequence
-// (Sec. 3.2, Eq. 6), mapped by Eq. 5 (Cartesian) or the log-polar map.
+// (Sec. 3.2, Eq. 6), mapped by Eq. 5 (Cartesian, scheme 0), the log-polar
+// map (1) or the square-to-disc map (3).
 __global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n,
                          int64_t K, double L, double fmin, double lr, double* __restrict__ fx,
                          double* __restrict__ fy, double* __restrict__ area) {
@@ -23,6 +24,23 @@ __global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
         fx[i] = L * (ux - 0.5);
         fy[i] = L * (uy - 0.5);
         area[i] = L * L / (double)K;
+    } else if (scheme == 3) {
+        // polar quasi-random frequencies (Sec. 3.2): concentric square-to-
+        // disc map of the point, disc radius L, equal cell areas
+        const double a = 2.0 * ux - 1.0, b = 2.0 * uy - 1.0;
+        double rad = 0.0, ang = 0.0;  // angle in half-turns
+        if (fabs(a) > fabs(b)) {
+            rad = a;
+            ang = 0.25 * (b / a);
+        } else if (b != 0.0) {
+            rad = b;
+            ang = 0.5 - 0.25 * (a / b);
+        }
+        double s, c;
+        sincospi(ang, &s, &c);
+        fx[i] = L * rad * c;
+        fy[i] = L * rad * s;
+        area[i] = 3.141592653589793 * L * L / (double)K;
     } else {
         double f = fmin * exp(lr * ux);
         double s, c;
@@ -690,7 +708,7 @@ hipError_t launch_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
                          int64_t K, int32_t N, double df, double fmin, double fmax, double* fx,
                          double* fy, double* area, hipStream_t st) {
     int64_t n = n_sets * K;
-    double L = (double)N * df;
+    double L = scheme == 3 ? fmax : (double)N * df;
     double lr = scheme == 1 ? log(fmax / fmin) : 0.0;
     hipLaunchKernelGGL(k_sample, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, scheme, s0x, s0y,
                        index, n, K, L, fmin, lr, fx, fy, area);

@@ -106,3 +106,21 @@ def test_no_cpu_fallback_without_gpu(q):
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         q.Context(0)
+
+
+def test_choose_cartesian_matches_oracle(q):
+    """The stopping rule for N (Sec. 4.3) in the library (host code, Gauss-
+    Legendre) against the oracle's (Simpson): same N, same variance."""
+    import oracle
+    for kw, D, d in (({"L0": 22.0}, 8.0, 1.1), ({"L0": 22.0}, None, 0.0),
+                     ({"L0": 50.0}, 1.8, 0.0)):
+        for eps in (1e-2, 1e-3, 1e-4):
+            ap = None if D is None else q.Aperture(D, d)
+            N, df, s2 = q.choose_cartesian(q.psd(0.1, kw["L0"]), ap, 0.0, eps)
+            assert df == 0.25 / kw["L0"]
+            rN, rs2 = oracle.choose_cartesian(df, eps, r0=0.1, L0=kw["L0"], D=D, d=d)
+            assert N == rN, (kw, D, eps, N, rN)
+            assert abs(s2 / rs2 - 1) < 1e-6
+    with pytest.raises(q.QrfsError) as e:
+        q.choose_cartesian(q.psd(0.1), None, 0.01, 1e-3)
+    assert e.value.status == q.ERR_UNSUPPORTED

@@ -82,6 +82,33 @@ def test_sampler_logpolar(q, ctx):
     assert np.max(np.abs(host(area) / ra - 1)) < 1e-14
 
 
+def test_sampler_disc(q, ctx):
+    """Polar quasi-random frequencies (square-to-disc map): points to 1e-14
+    of the radius, equal cell areas pi fmax^2 / K."""
+    n_sets, K, fmax = 3, 999, 0.25
+    s = q.disc_sampler(fmax, index=12345)
+    fx, fy, area = ctx.sample_frequencies(s, n_sets, K)
+    assert s.index == 12345 + n_sets * K
+    rx, ry, ra = oracle.sample_disc(n_sets, K, fmax, index=12345)
+    assert np.max(np.abs(host(fx) - rx)) < 1e-14 * fmax
+    assert np.max(np.abs(host(fy) - ry)) < 1e-14 * fmax
+    assert np.max(np.abs(host(area) / ra - 1)) < 1e-15
+
+
+@pytest.mark.parametrize("precision", [0, 3])
+def test_structure_function_disc_sampler(q, ctx, precision):
+    cfg = workloads.diffpiston()
+    K, R, R_block, fmax = 600, 300, 100, 0.5
+    s = q.disc_sampler(fmax, index=77)
+    sf, se = ctx.diff_piston_structure(q.psd(0.1, 25.0), q.Aperture(cfg["D"], 0.0),
+                                       dev(cfg["bx"]), dev(cfg["by"]), s, K, R, R_block,
+                                       rng=q.Rng(6, 0, 0), precision=precision)
+    fx, fy, area = oracle.sample_disc(3, K, fmax, index=77)
+    w = oracle.weights(fx, fy, area, r0=0.1, L0=25.0, D=cfg["D"])
+    rsf, _ = oracle.diff_piston_sf(fx, fy, w, cfg["bx"], cfg["by"], R, R_block, K=K, seed=6)
+    assert np.max(np.abs(host(sf) / rsf - 1)) < (1e-10 if precision == 0 else 2e-5)
+
+
 def test_sampler_continuation(q, ctx):
     """Two calls continue one sequence (Sec. 3.2: never reinitialised)."""
     s = q.logpolar_sampler(1e-3, 1e2)
