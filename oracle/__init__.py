@@ -55,6 +55,8 @@ def _load():
                                          _u64, _i32, _p, _p]),
         "oracle_temporal_sf": (None, [_p, _i64, _i64, _p, _p]),
         "oracle_concentric_map": (None, [_d, _d, _p, _p]),
+        "oracle_tilt": (None, [_i64, _p, _p, _p, _i64, _p, _p, _p, _p, _i64, _i64, _u64, _u64,
+                               _i32, _p, _i32, _p]),
         "oracle_sample_disc": (None, [_u64, _u64, _u64, _i64, _i64, _d, _p, _p, _p]),
         "oracle_choose_cartesian": (_i64, [_i32, _d, _d, _d, _i32, _d, _d, _d, _d, _p]),
         "oracle_temporal_experiment": (None, [_i64, _p, _p, _p, _p, _p, _p, _d, _i64, _i64,
@@ -216,6 +218,19 @@ def piston(fx, fy, w, cx, cy, D, d, R, R_block, K=None, seed=0, counter=0,
     out = np.zeros((R, cx.size))
     _load().oracle_piston(K, _ptr(fx), _ptr(fy), _ptr(w), cx.size, _ptr(cx), _ptr(cy), _ptr(D),
                           _ptr(d), R, R_block, seed, counter, mode, _ptr(coef), _ptr(out))
+    return out
+
+
+def tilt(fx, fy, w, cx, cy, D, d, R, R_block, axis=0, K=None, seed=0, counter=0,
+         mode=COEF_GAUSS_CS, coef=None):
+    """Aperture-averaged phase gradient (G-tilt, rad/m) along axis 0 (x) or
+    1 (y) at each aperture, [R][n_ap]; w is the unfiltered phase weight."""
+    fx, fy, w, cx, cy, D, d = map(_f64, (fx, fy, w, cx, cy, D, d))
+    K = fx.size if K is None else K
+    coef = None if coef is None else _f64(coef)
+    out = np.zeros((R, cx.size))
+    _load().oracle_tilt(K, _ptr(fx), _ptr(fy), _ptr(w), cx.size, _ptr(cx), _ptr(cy), _ptr(D),
+                        _ptr(d), R, R_block, seed, counter, mode, _ptr(coef), axis, _ptr(out))
     return out
 
 

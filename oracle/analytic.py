@@ -190,3 +190,16 @@ def temporal_sf_square(tau, B, v, r0, L0, D, d=0.0, half_width=0.25, c=None, mod
             u = v * t
             out[j] += 16.0 * np.sum(base * np.sin(np.pi * (FX * u[0] + FY * u[1])) ** 2)
     return out
+
+
+def tilt_variance(r0, L0, D, d=0.0, c=None, model=1, fmin=1e-12, fmax=None):
+    """One-axis variance of the aperture-averaged phase gradient (G-tilt),
+    rad^2/m^2: int d^2f W F^2 (2 pi f_x)^2 = 4 pi^3 int f^3 W F^2 df (for
+    Kolmogorov the integrand grows as f^(-2/3) at f -> 0: the band starts at
+    1e-12, which leaves out 3 (1e-12 D)^(1/3) of the scaled integral)."""
+    c = psd_constant() if c is None else c
+    fmax = fmax if fmax is not None else 400.0 / D
+
+    def g(f):
+        return f ** 3 * _psd(f, r0, L0, c, model) * aperture_filter(f, D, d) ** 2
+    return 4.0 * np.pi ** 3 * _integrate(g, fmin, fmax, D)

@@ -414,6 +414,48 @@ ORACLE_API void oracle_diff_piston_sf(int64_t K, const double* fx, const double*
 }
 
 /* ------------------------------------------------------------------ */
+/* Angle of arrival (aperture-averaged phase gradient, G-tilt): another  */
+/* linear filtering of the phase PSD (Sec. 2 names angle-of-arrival    */
+/* fluctuations among the quantities the method simulates)             */
+/* ------------------------------------------------------------------ */
+/* Gradient along axis (0: x, 1: y) of the piston of aperture j, i.e. the
+ * phase gradient averaged over the aperture: differentiating Eq. 3 with the
+ * filter F of Eq. 7 with respect to the centre gives
+ *   t_r(c) = sum_k w_k F(|f_k|) 2 pi f_axis,k (b_rk cos 2 pi f_k.c
+ *                                              - a_rk sin 2 pi f_k.c)
+ * in rad/m; the angle of arrival is lambda / (2 pi) times it. */
+ORACLE_API void oracle_tilt(int64_t K, const double* fx, const double* fy, const double* w,
+                            int64_t n_ap, const double* cx, const double* cy, const double* apD,
+                            const double* apd, int64_t R, int64_t R_block, uint64_t seed,
+                            uint64_t counter, int32_t mode, const double* coef, int32_t axis,
+                            double* tilt) {
+#pragma omp parallel
+    {
+        double* c = (double*)malloc(sizeof(double) * (size_t)(2 * K));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t r = 0; r < R; ++r) {
+            int64_t s = r / R_block;
+            const double* cr = c;
+            if (coef) cr = coef + r * 2 * K;
+            else oracle_coefficients(seed, counter + (uint64_t)r, K, mode, c);
+            for (int64_t j = 0; j < n_ap; ++j) {
+                double acc = 0.0;
+                for (int64_t k = 0; k < K; ++k) {
+                    int64_t i = s * K + k;
+                    double f = sqrt(fx[i] * fx[i] + fy[i] * fy[i]);
+                    double arg = 2.0 * M_PI * (fx[i] * cx[j] + fy[i] * cy[j]);
+                    double g = 2.0 * M_PI * (axis == 0 ? fx[i] : fy[i]);
+                    double amp = w[i] * oracle_aperture_filter(apD[j], apd[j], f) * g;
+                    acc += amp * (cr[2 * k + 1] * cos(arg) - cr[2 * k] * sin(arg));
+                }
+                tilt[r * n_ap + j] = acc;
+            }
+        }
+        free(c);
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Hyper-parameters of the Cartesian sampling (Sec. 4.3)                */
 /* ------------------------------------------------------------------ */
 /* g(x) = int_0^x f W(f) F(f)^2 df (the radial integral of the filtered
