@@ -257,6 +257,23 @@ QRFS_API qrfs_status qrfs_piston(qrfs_context* ctx, int64_t K, const double* fx,
                         const qrfs_rng* rng, const double* coef, int32_t precision,
                         void* piston, void* stream);
 
+/* Angle of arrival (G-tilt): the phase gradient averaged over each aperture,
+ * along the direction (ux, uy), in rad/m (times lambda / (2 pi) for the
+ * angle in radians).  Sec. 2 counts angle-of-arrival fluctuations among the
+ * linear functionals of the phase the method simulates; the average of the
+ * gradient over the aperture is the gradient of the piston with respect to
+ * the centre, so differentiating Eq. 3 with the filter of Eq. 7 gives
+ *   tilt[r][j] = sum_k w_k F_j(|f_k|) 2 pi (u.f_k)
+ *                (b_rk cos 2 pi f_k.c_j - a_rk sin 2 pi f_k.c_j).
+ * (ux, uy) need not be a unit vector (the result scales with it).  Arguments,
+ * layouts and errors as qrfs_piston; extra error: (ux, uy) zero or not
+ * finite. */
+QRFS_API qrfs_status qrfs_tilt(qrfs_context* ctx, int64_t K, const double* fx, const double* fy,
+                      const double* w, int64_t n_ap, const double* cx, const double* cy,
+                      const double* apD, const double* apd, double ux, double uy, int64_t R,
+                      int64_t R_block, const qrfs_rng* rng, const double* coef,
+                      int32_t precision, void* tilt, void* stream);
+
 /* Differential pistons between two equal apertures, one at the origin and
  * one at baseline b (Sec. 4.4): dp[r][b] = p_r(bx[b], by[b]) - p_r(0, 0),
  * evaluated directly as sum_k w_k [a (cos 2 pi f.B - 1) + b sin 2 pi f.B].

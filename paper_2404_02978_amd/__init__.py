@@ -151,6 +151,8 @@ def load_library():
                                       ctypes.POINTER(Rng), _P, _I32, _P, _P]),
         "qrfs_piston": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _I64,
                             ctypes.POINTER(Rng), _P, _I32, _P, _P]),
+        "qrfs_tilt": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, ctypes.c_double,
+                          ctypes.c_double, _I64, _I64, ctypes.POINTER(Rng), _P, _I32, _P, _P]),
         "qrfs_diff_piston": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _I64, _I64,
                                  ctypes.POINTER(Rng), _P, _I32, _P, _P]),
         "qrfs_diff_piston_structure_sets": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _I64, _I64,
@@ -318,6 +320,22 @@ class Context:
             _dev_f64(apD, "apD", n_ap), _dev_f64(apd, "apd", n_ap), R, R_block,
             self._rng(rng, coef), None if coef is None else _dev_f64(coef, "coef", R * 2 * K),
             precision, _ptr(out), _stream()))
+        return out
+
+    def tilt(self, K, fx, fy, w, cx, cy, apD, apd, u, R, R_block, rng=None, coef=None,
+             precision=PREC_FP32, out=None):
+        """Aperture-averaged phase gradient along u = (ux, uy), rad/m
+        (G-tilt; w is the unfiltered phase weight).  [R][n_ap]."""
+        n_sets = math.ceil(R / R_block)
+        n_ap = cx.numel()
+        out = self._out(R, n_ap, precision) if out is None else out
+        _check(load_library().qrfs_tilt(
+            self._h, K, _dev_f64(fx, "fx", n_sets * K), _dev_f64(fy, "fy", n_sets * K),
+            _dev_f64(w, "w", n_sets * K), n_ap, _dev_f64(cx, "cx"), _dev_f64(cy, "cy", n_ap),
+            _dev_f64(apD, "apD", n_ap), _dev_f64(apd, "apd", n_ap), float(u[0]), float(u[1]),
+            R, R_block, self._rng(rng, coef),
+            None if coef is None else _dev_f64(coef, "coef", R * 2 * K), precision, _ptr(out),
+            _stream()))
         return out
 
     def diff_piston(self, K, fx, fy, w, bx, by, R, R_block, rng=None, coef=None,

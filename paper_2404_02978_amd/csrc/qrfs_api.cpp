@@ -279,7 +279,8 @@ qrfs_status sum_entry(qrfs_context* ctx, int basis, int64_t K, const double* fx,
                       const double* fy, const double* w, int64_t P, const double* px,
                       const double* py, const double* apD, const double* apd, int64_t R,
                       int64_t R_block, const qrfs_rng* rng, const double* coef,
-                      int32_t precision, void* out, void* stream) {
+                      int32_t precision, void* out, void* stream,
+                      const double* grad_u = nullptr) {
     qrfs_status s = check_sum_common(K, P, R, R_block, rng, coef, precision);
     if (s) return s;
     CHECK_PTR(fx);
@@ -318,6 +319,11 @@ qrfs_status sum_entry(qrfs_context* ctx, int basis, int64_t K, const double* fx,
     a.ksplit = 1;
     a.kspan = K;
     a.phi_part = nullptr;
+    if (grad_u) {
+        a.grad = 1;
+        a.gx = 2.0 * M_PI * grad_u[0];
+        a.gy = 2.0 * M_PI * grad_u[1];
+    }
     if (use_wide(ctx, precision, P, R, R_block))
         s = wide_sum(ctx, precision, basis, a, cdiv(R, R_block), (hipStream_t)stream);
     else
@@ -470,6 +476,18 @@ qrfs_status qrfs_piston(qrfs_context* ctx, int64_t K, const double* fx, const do
                         void* piston, void* stream) {
     return sum_entry(ctx, qrfs::BASIS_PISTON, K, fx, fy, w, n_ap, cx, cy, apD, apd, R, R_block,
                      rng, coef, precision, piston, stream);
+}
+
+qrfs_status qrfs_tilt(qrfs_context* ctx, int64_t K, const double* fx, const double* fy,
+                      const double* w, int64_t n_ap, const double* cx, const double* cy,
+                      const double* apD, const double* apd, double ux, double uy, int64_t R,
+                      int64_t R_block, const qrfs_rng* rng, const double* coef,
+                      int32_t precision, void* tilt, void* stream) {
+    if (!std::isfinite(ux) || !std::isfinite(uy) || (ux == 0.0 && uy == 0.0))
+        return fail(QRFS_ERR_INVALID_ARG, "direction (%g, %g) is zero or not finite", ux, uy);
+    const double u[2] = {ux, uy};
+    return sum_entry(ctx, qrfs::BASIS_PISTON, K, fx, fy, w, n_ap, cx, cy, apD, apd, R, R_block,
+                     rng, coef, precision, tilt, stream, u);
 }
 
 qrfs_status qrfs_diff_piston(qrfs_context* ctx, int64_t K, const double* fx, const double* fy,

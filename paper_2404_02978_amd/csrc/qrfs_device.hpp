@@ -168,4 +168,15 @@ __device__ __forceinline__ double aperture_filter(double D, double d, double f) 
 // Fractional part of t to [-1/2, 1/2] in binary64 (exact).
 __device__ __forceinline__ double frac_centered(double t) { return t - rint(t); }
 
+// Piston basis: the amplitude factor and the argument shift (cycles) that
+// turn the piston into its gradient along u when `grad` is set, with
+// (gx, gy) = 2 pi u (d/dc [a cos 2 pi f.c + b sin 2 pi f.c]
+// = 2 pi (u.f) [b cos - a sin], the same pair a quarter cycle on);
+// 1 and 0 otherwise.
+__device__ __forceinline__ double grad_factor(int32_t grad, double gx, double gy, double fx,
+                                              double fy) {
+    return grad ? gx * fx + gy * fy : 1.0;
+}
+__device__ __forceinline__ double grad_shift(int32_t grad) { return grad ? 0.25 : 0.0; }
+
 }  // namespace qrfs

@@ -47,6 +47,11 @@ struct SumArgs {
     int32_t ksplit;      // frequency ranges per row tile (MFMA kernels, EPI_SFSUM)
     int64_t kspan;       // frequencies per range (multiple of the chunk length)
     float* phi_part;     // EPI_SFSUM, ksplit > 1: [ksplit][R][P] partial sums
+    // BASIS_PISTON, grad != 0: the gradient of the piston along u (G-tilt)
+    // instead of the piston: amplitudes times gx f_x + gy f_y with
+    // (gx, gy) = 2 pi u, arguments shifted by a quarter cycle
+    int32_t grad;
+    double gx, gy;
 };
 
 // The two-phase contraction (wide point sets) over the sets [s.set0,

@@ -168,6 +168,7 @@ __global__ __launch_bounds__(256) void k_sum_f64(SumArgs a, int64_t row_tiles,
             int kk = i / F64_TP;
             int pp = i % F64_TP;
             double t = sfx[kk] * spx[pp] + sfy[kk] * spy[pp];
+            if (BASIS == BASIS_PISTON) t += grad_shift(a.grad);
             double rf = frac_centered(t);
             double s, c;
             if (BASIS == BASIS_DIFF) {
@@ -179,7 +180,8 @@ __global__ __launch_bounds__(256) void k_sum_f64(SumArgs a, int64_t row_tiles,
             }
             double amp = sw[kk];
             if (BASIS == BASIS_PISTON)
-                amp *= aperture_filter(sD[pp], sd[pp], sqrt(sfx[kk] * sfx[kk] + sfy[kk] * sfy[kk]));
+                amp *= aperture_filter(sD[pp], sd[pp], sqrt(sfx[kk] * sfx[kk] + sfy[kk] * sfy[kk])) *
+                       grad_factor(a.grad, a.gx, a.gy, sfx[kk], sfy[kk]);
             sBc[kk][pp] = amp * c;
             sBs[kk][pp] = amp * s;
         }
@@ -401,11 +403,14 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
         }
         // basis of this chunk into buffer `buf`
         const double fmag = BASIS == BASIS_PISTON ? sqrt(cfx * cfx + cfy * cfy) : 0.0;
+        const double gw =
+            BASIS == BASIS_PISTON ? cw * grad_factor(a.grad, a.gx, a.gy, cfx, cfy) : cw;
+        const double sh = BASIS == BASIS_PISTON ? grad_shift(a.grad) : 0.0;
         for (int pp = pp0; pp < NT; pp += cstep) {
-            double amp = cw;
+            double amp = gw;
             if (BASIS == BASIS_PISTON) amp *= aperture_filter(sD[pp], sd[pp], fmag);
             float cb, sb;
-            basis_pair<BASIS>(cfx * spx[pp] + cfy * spy[pp], amp, cb, sb);
+            basis_pair<BASIS>(cfx * spx[pp] + cfy * spy[pp] + sh, amp, cb, sb);
             if constexpr (PREC == 1) {
                 float* dst = sBf + buf * NT * STR_F32 + pp * STR_F32 + 2 * kk;
                 dst[0] = cb;

@@ -257,8 +257,13 @@ struct WideTile {
             const double cfx = bcast_lane(f0, kk);
             const double cfy = bcast_lane(f1, kk);
             double amp = bcast_lane(f2, kk);
-            if (BASIS == BASIS_PISTON) amp *= aperture_filter(pD, pd, sqrt(cfx * cfx + cfy * cfy));
-            basis_pair<BASIS>(cfx * px + cfy * py, amp, v[2 * i], v[2 * i + 1]);
+            double t = cfx * px + cfy * py;
+            if (BASIS == BASIS_PISTON) {
+                amp *= aperture_filter(pD, pd, sqrt(cfx * cfx + cfy * cfy)) *
+                       grad_factor(a.grad, a.gx, a.gy, cfx, cfy);
+                t += grad_shift(a.grad);
+            }
+            basis_pair<BASIS>(t, amp, v[2 * i], v[2 * i + 1]);
         }
         const int col = threadIdx.x & (WT - 1);
         if constexpr (PREC == 1) {

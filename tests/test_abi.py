@@ -66,6 +66,13 @@ def test_argument_checks_precede_device_use(q):
     st = lib.qrfs_piston(None, 3, ctypes.c_void_p(12), p, p, 2, p, p, p, p, 5, 5,
                          ctypes.byref(rng), None, 1, p, None)
     assert st == q.ERR_INVALID_ARG and b"aligned" in lib.qrfs_last_error_detail()
+    # tilt: zero direction, then valid arguments reaching the NULL context
+    st = lib.qrfs_tilt(None, 3, p, p, p, 2, p, p, p, p, 0.0, 0.0, 5, 5, ctypes.byref(rng), None,
+                       1, p, None)
+    assert st == q.ERR_INVALID_ARG and b"direction" in lib.qrfs_last_error_detail()
+    st = lib.qrfs_tilt(None, 3, p, p, p, 2, p, p, p, p, 0.0, 1.0, 5, 5, ctypes.byref(rng), None,
+                       1, p, None)
+    assert st == q.ERR_INVALID_ARG and b"context" in lib.qrfs_last_error_detail()
     # bad PSD / aperture
     psd = q.psd(0.1, -3.0)
     st = lib.qrfs_weights(None, ctypes.byref(psd), None, 3, p, p, p, p, None)
