@@ -63,7 +63,7 @@ typedef int32_t qrfs_status;
 #define QRFS_ERR_DEVICE (-3)        /* HIP runtime error (launch, fault)      */
 #define QRFS_ERR_UNSUPPORTED (-4)   /* valid but not implemented combination  */
 
-#define QRFS_ABI_VERSION 1
+#define QRFS_ABI_VERSION 2
 
 /* Static string for a status code. */
 QRFS_API const char* qrfs_error_string(qrfs_status s);
@@ -430,8 +430,11 @@ QRFS_API qrfs_status qrfs_proposal_save(const qrfs_proposal* p, const char* path
 QRFS_API qrfs_status qrfs_proposal_load(qrfs_proposal* p, const char* path);
 
 /* ------------------------------------------------------ batched launches */
-/* Many uneven phase-field instances in one persistent launch (the phase of
- * Eq. 3 at each instance's points, as qrfs_synthesize_phase computes it).
+/* Many uneven instances in one persistent launch: the phase of Eq. 3 at
+ * each instance's points, as qrfs_synthesize_phase computes it, or, for an
+ * instance that brings aperture diameters, the pistons of apertures
+ * (filled or annular) centred at the points, as qrfs_piston computes them,
+ * or their G-tilts along (ux, uy), as qrfs_tilt computes them.
  * Each instance brings its own PSD, sampler (the instance draws
  * ceil(R/R_block) sets of K frequencies starting at sampler.index), points,
  * realisations and output.  The batch owns the frequency buffers; executing
@@ -450,7 +453,15 @@ typedef struct {
     int64_t R;            /* realisations                               */
     int64_t R_block;      /* realisations per frequency set, in [1, R]  */
     qrfs_rng rng;         /* coefficient stream (GAUSS_CS or EQ3)       */
-    float* phase;         /* device float[R][P] output                  */
+    float* phase;         /* device float[R][P] output (phase, pistons
+                             or tilts)                                  */
+    const double* apD;    /* NULL: phase at the points; else device
+                             double[P] outer diameters D > 0 of the
+                             apertures centred at the points            */
+    const double* apd;    /* with apD: device double[P] inner diameters
+                             0 <= d < D (0: filled); NULL otherwise     */
+    double ux, uy;        /* with apD: (0, 0) for pistons, else the
+                             direction of the G-tilt; 0 without apD     */
 } qrfs_batch_instance;
 
 typedef struct qrfs_batch qrfs_batch;
@@ -459,7 +470,9 @@ typedef struct qrfs_batch qrfs_batch;
  * QRFS_PREC_FP32, QRFS_PREC_SPLIT_BF16 or QRFS_PREC_BF16X6 (FP64 ->
  * QRFS_ERR_UNSUPPORTED).  Allocates the batch's device buffers.
  * Errors: n <= 0 or > 65535, any instance invalid as for
- * qrfs_synthesize_phase / qrfs_sample_frequencies / qrfs_weights. */
+ * qrfs_synthesize_phase / qrfs_sample_frequencies / qrfs_weights /
+ * qrfs_piston / qrfs_tilt; apD and apd not both NULL or both set; a
+ * direction without apertures; a direction not finite. */
 QRFS_API qrfs_status qrfs_batch_create(qrfs_context* ctx, int64_t n,
                                        const qrfs_batch_instance* inst, int32_t precision,
                                        qrfs_batch** out);

@@ -67,7 +67,9 @@ class Rng(ctypes.Structure):
 class BatchInstance(ctypes.Structure):
     _fields_ = [("psd", Psd), ("sampler", Sampler), ("K", ctypes.c_int64), ("P", ctypes.c_int64),
                 ("px", ctypes.c_void_p), ("py", ctypes.c_void_p), ("R", ctypes.c_int64),
-                ("R_block", ctypes.c_int64), ("rng", Rng), ("phase", ctypes.c_void_p)]
+                ("R_block", ctypes.c_int64), ("rng", Rng), ("phase", ctypes.c_void_p),
+                ("apD", ctypes.c_void_p), ("apd", ctypes.c_void_p), ("ux", ctypes.c_double),
+                ("uy", ctypes.c_double)]
 
 
 def psd(r0, L0=None, model=None, c=0.0):
@@ -416,10 +418,13 @@ class Context:
 
 
 class Batch:
-    """Many uneven phase-field instances in one persistent launch.
+    """Many uneven instances in one persistent launch.
 
     instances: list of dicts with keys psd, sampler, K, px, py (float64 CUDA
-    tensors), R, R_block, rng; outputs are allocated here (float32 [R][P]).
+    tensors), R, R_block, rng; optional apD, apd (float64 CUDA tensors [P]:
+    pistons of apertures centred at the points instead of the phase) and u
+    (with apertures: G-tilts along u instead of pistons).  Outputs are
+    allocated here (float32 [R][P]).
     """
 
     def __init__(self, ctx, instances, precision=PREC_BF16X6):
@@ -434,9 +439,16 @@ class Batch:
             out = torch.empty((d["R"], P), dtype=torch.float32, device=ctx.device)
             self.outputs.append(out)
             self._keep += [px, py]
+            apD, apd = d.get("apD"), d.get("apd")
+            if apD is not None:
+                self._keep += [apD, apd]
+            ux, uy = d.get("u", (0.0, 0.0))
             arr[i] = BatchInstance(d["psd"], d["sampler"], d["K"], P, _dev_f64(px, "px"),
                                    _dev_f64(py, "py", P), d["R"], d.get("R_block", d["R"]),
-                                   d.get("rng", Rng(0, 0, COEF_GAUSS_CS)), _ptr(out))
+                                   d.get("rng", Rng(0, 0, COEF_GAUSS_CS)), _ptr(out),
+                                   None if apD is None else _dev_f64(apD, "apD", P),
+                                   None if apd is None else _dev_f64(apd, "apd", P),
+                                   float(ux), float(uy))
         h = _P()
         _check(lib.qrfs_batch_create(ctx.handle, len(instances), arr, precision, ctypes.byref(h)))
         self._h = h

@@ -1,5 +1,5 @@
-// qrfs_batch.cpp -- batched persistent launches of uneven phase-field
-// instances: work list (longest items first), autotuned launch shape, and
+// qrfs_batch.cpp -- batched persistent launches of uneven phase-field,
+// piston and tilt instances: work list (longest items first), autotuned launch shape, and
 // HIP graph capture of the whole sequence.
 #include <hip/hip_runtime.h>
 
@@ -42,6 +42,7 @@ struct qrfs_batch {
     std::vector<double*> fx, fy, area, w;
     int n_items = 0;
     int shape = 0;
+    bool has_ap = false;  // some instance computes pistons or tilts
     int n_cu = 256;
     // two-phase form: coefficient tiles of every instance and its launch
     // arguments (allocated on first use of the two-phase shape)
@@ -115,6 +116,17 @@ qrfs_status check_instance(const qrfs_batch_instance& in, int64_t i) {
         return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: misaligned array", (long long)i);
     if (in.rng.mode != QRFS_COEF_GAUSS_CS && in.rng.mode != QRFS_COEF_EQ3)
         return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: unknown coefficient mode",
+                        (long long)i);
+    if (!in.apD != !in.apd)
+        return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: apD and apd go together",
+                        (long long)i);
+    if (((uintptr_t)in.apD & 7) || ((uintptr_t)in.apd & 7))
+        return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: misaligned array", (long long)i);
+    if (!std::isfinite(in.ux) || !std::isfinite(in.uy))
+        return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: direction not finite",
+                        (long long)i);
+    if (!in.apD && (in.ux != 0.0 || in.uy != 0.0))
+        return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: a tilt direction needs apertures",
                         (long long)i);
     return QRFS_OK;
 }
@@ -243,11 +255,11 @@ qrfs_status enqueue(qrfs_batch* b, hipStream_t st) {
             e = qrfs::launch_wide_coef(b->precision, b->wargs[i], st);
             if (e != hipSuccess) return hfail(e, "coefficient tile launch");
         }
-        e = qrfs::launch_wide_batch(b->precision, b->d_wargs, b->d_items, b->n_items,
+        e = qrfs::launch_wide_batch(b->precision, b->has_ap, b->d_wargs, b->d_items, b->n_items,
                                     b->d_counter, blocks, st);
     } else {
-        e = qrfs::launch_batch(b->precision, sh, b->d_args, b->d_items, b->n_items, b->d_counter,
-                               blocks, st);
+        e = qrfs::launch_batch(b->precision, sh, b->has_ap, b->d_args, b->d_items, b->n_items,
+                               b->d_counter, blocks, st);
     }
     if (e != hipSuccess) return hfail(e, "persistent launch");
     return QRFS_OK;
@@ -335,6 +347,16 @@ qrfs_status qrfs_batch_create(qrfs_context* ctx, int64_t n, const qrfs_batch_ins
         a.out = in.phase;
         a.ksplit = 1;
         a.kspan = in.K;
+        if (in.apD) {
+            a.apD = in.apD;
+            a.apd = in.apd;
+            b->has_ap = true;
+            if (in.ux != 0.0 || in.uy != 0.0) {
+                a.grad = 1;
+                a.gx = 2.0 * M_PI * in.ux;
+                a.gy = 2.0 * M_PI * in.uy;
+            }
+        }
         b->args.push_back(a);
     }
     e = hipMemcpy(b->d_args, b->args.data(), sizeof(qrfs::SumArgs) * b->n, hipMemcpyHostToDevice);

@@ -111,15 +111,18 @@ BatchShape batch_shape(int precision, int id);
 
 // Resets the work counter and launches the persistent kernel (256 threads
 // per block, n_blocks blocks) over items[0 .. n_items).
-hipError_t launch_batch(int precision, BatchShape shape, const SumArgs* inst,
+// has_ap: some instance carries apertures (a.apD set), and the kernel
+// chooses the piston basis for its items.
+hipError_t launch_batch(int precision, BatchShape shape, bool has_ap, const SumArgs* inst,
                         const BatchItem* items, int n_items, unsigned* counter, int n_blocks,
                         hipStream_t st);
 
 // Resets the work counter and launches the persistent two-phase kernel
 // (n_blocks blocks) over items[0 .. n_items) of the instances `inst`
 // (device array; coefficient tiles already written).
-hipError_t launch_wide_batch(int precision, const WideArgs* inst, const BatchItem* items,
-                             int n_items, unsigned* counter, int n_blocks, hipStream_t st);
+hipError_t launch_wide_batch(int precision, bool has_ap, const WideArgs* inst,
+                             const BatchItem* items, int n_items, unsigned* counter, int n_blocks,
+                             hipStream_t st);
 hipError_t launch_reset_counter(unsigned* counter, hipStream_t st);
 
 // squares of the K-range partial sums, summed per column over blocks of

@@ -595,13 +595,15 @@ __global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
 }
 
 // ----------------------------------------------------- batch kernels ----
-// Persistent batch of uneven phase-field instances: a grid sized to the chip
-// pulls work items (instance, set, row tile, column tile) from a global
-// counter until the list is exhausted.  Items are ordered by decreasing
-// cost (longest first), so the tail of the launch is made of small items.
-// The counter is advanced with a vector atomic by one lane; every wave of
-// every block reaches the exit test on each iteration.
-template <int PREC, int MW, int NB>
+// Persistent batch of uneven instances: a grid sized to the chip pulls work
+// items (instance, set, row tile, column tile) from a global counter until
+// the list is exhausted.  Items are ordered by decreasing cost (longest
+// first), so the tail of the launch is made of small items.  The counter is
+// advanced with a vector atomic by one lane; every wave of every block
+// reaches the exit test on each iteration.  AP: some instances carry
+// apertures (pistons or tilts, chosen per item from the instance); without
+// it every item is a phase item.
+template <int PREC, int MW, int NB, bool AP>
 __global__ __launch_bounds__(256) void k_batch_persistent(const SumArgs* __restrict__ inst,
                                                           const BatchItem* __restrict__ items,
                                                           int n_items,
@@ -618,10 +620,20 @@ __global__ __launch_bounds__(256) void k_batch_persistent(const SumArgs* __restr
         const SumArgs a = inst[w.inst];
         const int64_t row_tiles = (a.R_block + 32 * MW * (blockDim.x >> 6) - 1) /
                                   (32 * MW * (blockDim.x >> 6));
-        if (a.mode == 0)
+        bool piston = false;
+        if constexpr (AP) piston = a.apD != nullptr;
+        if (piston) {
+            if (a.mode == 0)
+                sum_tile<PREC, BASIS_PISTON, EPI_STORE, MW, NB, 0>(a, row_tiles, w.set, w.rt, w.ct,
+                                                                   0, sm);
+            else
+                sum_tile<PREC, BASIS_PISTON, EPI_STORE, MW, NB, 1>(a, row_tiles, w.set, w.rt, w.ct,
+                                                                   0, sm);
+        } else if (a.mode == 0) {
             sum_tile<PREC, BASIS_PHASE, EPI_STORE, MW, NB, 0>(a, row_tiles, w.set, w.rt, w.ct, 0, sm);
-        else
+        } else {
             sum_tile<PREC, BASIS_PHASE, EPI_STORE, MW, NB, 1>(a, row_tiles, w.set, w.rt, w.ct, 0, sm);
+        }
         __syncthreads();
     }
 }
@@ -871,39 +883,45 @@ BatchShape batch_shape(int precision, int id) {
 }
 
 template <int PREC, int MW, int NB>
-static hipError_t launch_batch_t(const SumArgs* inst, const BatchItem* items, int n_items,
+static hipError_t launch_batch_t(bool ap, const SumArgs* inst, const BatchItem* items, int n_items,
                                  unsigned* counter, int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_batch_persistent<PREC, MW, NB>), dim3((unsigned)n_blocks), dim3(256), 0,
-                       st, inst, items, n_items, counter);
+    if (ap)
+        hipLaunchKernelGGL((k_batch_persistent<PREC, MW, NB, true>), dim3((unsigned)n_blocks),
+                           dim3(256), 0, st, inst, items, n_items, counter);
+    else
+        hipLaunchKernelGGL((k_batch_persistent<PREC, MW, NB, false>), dim3((unsigned)n_blocks),
+                           dim3(256), 0, st, inst, items, n_items, counter);
     return hipGetLastError();
 }
 
 template <int PREC>
-static hipError_t launch_batch_p(int MW, int NB, const SumArgs* inst, const BatchItem* items,
-                                 int n_items, unsigned* counter, int n_blocks, hipStream_t st) {
+static hipError_t launch_batch_p(int MW, int NB, bool ap, const SumArgs* inst,
+                                 const BatchItem* items, int n_items, unsigned* counter,
+                                 int n_blocks, hipStream_t st) {
     if (MW == 2 && NB == 2) {
         if constexpr (PREC != 1)
-            return launch_batch_t<PREC, 2, 2>(inst, items, n_items, counter, n_blocks, st);
+            return launch_batch_t<PREC, 2, 2>(ap, inst, items, n_items, counter, n_blocks, st);
         return hipErrorInvalidValue;
     }
     if (MW == 1 && NB == 2)
-        return launch_batch_t<PREC, 1, 2>(inst, items, n_items, counter, n_blocks, st);
+        return launch_batch_t<PREC, 1, 2>(ap, inst, items, n_items, counter, n_blocks, st);
     if (MW == 1 && NB == 1)
-        return launch_batch_t<PREC, 1, 1>(inst, items, n_items, counter, n_blocks, st);
+        return launch_batch_t<PREC, 1, 1>(ap, inst, items, n_items, counter, n_blocks, st);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch(int precision, BatchShape shape, const SumArgs* inst,
+hipError_t launch_batch(int precision, BatchShape shape, bool has_ap, const SumArgs* inst,
                         const BatchItem* items, int n_items, unsigned* counter, int n_blocks,
                         hipStream_t st) {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const int MW = shape.MW, NB = shape.NB;
     if (precision == 1)
-        return launch_batch_p<1>(shape.MW, shape.NB, inst, items, n_items, counter, n_blocks, st);
+        return launch_batch_p<1>(MW, NB, has_ap, inst, items, n_items, counter, n_blocks, st);
     if (precision == 2)
-        return launch_batch_p<2>(shape.MW, shape.NB, inst, items, n_items, counter, n_blocks, st);
-    return launch_batch_p<3>(shape.MW, shape.NB, inst, items, n_items, counter, n_blocks, st);
+        return launch_batch_p<2>(MW, NB, has_ap, inst, items, n_items, counter, n_blocks, st);
+    return launch_batch_p<3>(MW, NB, has_ap, inst, items, n_items, counter, n_blocks, st);
 }
 
 hipError_t launch_sfsum_rows(const float* phi, int ksplit, int64_t R, int64_t P, double* partial,

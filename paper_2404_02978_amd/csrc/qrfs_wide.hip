@@ -459,12 +459,14 @@ __global__ __launch_bounds__(64 * WV) void k_wide(WideArgs wa) {
     wide_tile_run<PREC, BASIS, WV>(sm, wa, sl, rt, ct);
 }
 
-// Persistent batch of uneven phase-field instances (two-phase form): one
-// block per CU pulls work items (instance, set, 256-row tile, 256-column
-// tile) from a global counter until the list is exhausted; items come
-// longest first.  The counter is advanced with a vector atomic by one lane,
-// and every wave reaches the exit test on each iteration.
-template <int PREC, int WV>
+// Persistent batch of uneven instances (two-phase form): one block per CU
+// pulls work items (instance, set, 256-row tile, 256-column tile) from a
+// global counter until the list is exhausted; items come longest first.
+// The counter is advanced with a vector atomic by one lane, and every wave
+// reaches the exit test on each iteration.  AP: some instances carry
+// apertures (pistons or tilts, chosen per item); without it every item is
+// a phase item.
+template <int PREC, int WV, bool AP>
 __global__ __launch_bounds__(64 * WV) void k_wide_batch(const WideArgs* __restrict__ inst,
                                                         const BatchItem* __restrict__ items,
                                                         int n_items,
@@ -479,7 +481,12 @@ __global__ __launch_bounds__(64 * WV) void k_wide_batch(const WideArgs* __restri
         if (it >= n_items) break;
         const BatchItem w = items[it];
         const WideArgs wa = inst[w.inst];
-        wide_tile_run<PREC, BASIS_PHASE, WV>(sm, wa, w.set, w.rt, w.ct);
+        bool piston = false;
+        if constexpr (AP) piston = wa.s.apD != nullptr;
+        if (piston)
+            wide_tile_run<PREC, BASIS_PISTON, WV>(sm, wa, w.set, w.rt, w.ct);
+        else
+            wide_tile_run<PREC, BASIS_PHASE, WV>(sm, wa, w.set, w.rt, w.ct);
         __syncthreads();
     }
 }
@@ -528,21 +535,30 @@ static hipError_t launch_sum_p(int basis, const WideArgs& wa, hipStream_t st) {
 }
 
 template <int PREC>
-static hipError_t launch_wide_batch_t(const WideArgs* inst, const BatchItem* items, int n_items,
-                                      unsigned* counter, int n_blocks, hipStream_t st) {
+static hipError_t launch_wide_batch_t(bool ap, const WideArgs* inst, const BatchItem* items,
+                                      int n_items, unsigned* counter, int n_blocks,
+                                      hipStream_t st) {
     constexpr int WV = QRFS_WIDE_WAVES;
-    hipLaunchKernelGGL((k_wide_batch<PREC, WV>), dim3((unsigned)n_blocks), dim3(64 * WV), 0, st,
-                       inst, items, n_items, counter);
+    if (ap)
+        hipLaunchKernelGGL((k_wide_batch<PREC, WV, true>), dim3((unsigned)n_blocks), dim3(64 * WV),
+                           0, st, inst, items, n_items, counter);
+    else
+        hipLaunchKernelGGL((k_wide_batch<PREC, WV, false>), dim3((unsigned)n_blocks),
+                           dim3(64 * WV), 0, st, inst, items, n_items, counter);
     return hipGetLastError();
 }
 
-hipError_t launch_wide_batch(int precision, const WideArgs* inst, const BatchItem* items,
-                             int n_items, unsigned* counter, int n_blocks, hipStream_t st) {
+hipError_t launch_wide_batch(int precision, bool has_ap, const WideArgs* inst,
+                             const BatchItem* items, int n_items, unsigned* counter, int n_blocks,
+                             hipStream_t st) {
     hipError_t e = launch_reset_counter(counter, st);
     if (e != hipSuccess) return e;
-    if (precision == 1) return launch_wide_batch_t<1>(inst, items, n_items, counter, n_blocks, st);
-    if (precision == 2) return launch_wide_batch_t<2>(inst, items, n_items, counter, n_blocks, st);
-    if (precision == 3) return launch_wide_batch_t<3>(inst, items, n_items, counter, n_blocks, st);
+    if (precision == 1)
+        return launch_wide_batch_t<1>(has_ap, inst, items, n_items, counter, n_blocks, st);
+    if (precision == 2)
+        return launch_wide_batch_t<2>(has_ap, inst, items, n_items, counter, n_blocks, st);
+    if (precision == 3)
+        return launch_wide_batch_t<3>(has_ap, inst, items, n_items, counter, n_blocks, st);
     return hipErrorInvalidValue;
 }
 

@@ -137,3 +137,76 @@ def test_batch_rejects_bad_instances(q, ctx):
     with pytest.raises(q.QrfsError) as e:
         q.Batch(ctx, inst[:2], precision=0)
     assert e.value.status == q.ERR_UNSUPPORTED
+
+
+# ------------------------------------------- apertures in the batch ----
+
+def aperture_instances(q):
+    """Phase instances mixed with pistons of annular and filled apertures
+    (ragged against every column tile: 300 = 256 + 44) and G-tilts along x
+    and along an oblique direction."""
+    inst, refs = instances(q, 3)
+    rng = np.random.default_rng(21)
+    for j, u in enumerate([None, (1.0, 0.0), (0.6, -0.8)]):
+        P, K, R, R_block = 300 - 37 * j, 203 - 40 * j, 90, 45
+        cx, cy = rng.uniform(-60, 60, P), rng.uniform(-60, 60, P)
+        D = rng.choice([8.0, 1.8, 4.0], P)
+        d = np.where(D > 3.0, 1.1, 0.0)
+        index, seed, counter = 50000 + 7000 * j, 4 + j, 300 * j
+        s = q.logpolar_sampler(1e-3, 1e2, index=index)
+        d_in = dict(psd=q.psd(0.1, 25.0), sampler=s, K=K, px=dev(cx), py=dev(cy), R=R,
+                    R_block=R_block, rng=q.Rng(seed, counter, q.COEF_GAUSS_CS), apD=dev(D),
+                    apd=dev(d))
+        if u is not None:
+            d_in["u"] = u
+        inst.append(d_in)
+        n_sets = math.ceil(R / R_block)
+        fx, fy, area = oracle.sample_logpolar(n_sets, K, 1e-3, 1e2, index=index)
+        w = oracle.weights(fx, fy, area, r0=0.1, L0=25.0)
+        if u is None:
+            refs.append(oracle.piston(fx, fy, w, cx, cy, D, d, R, R_block, K=K, seed=seed,
+                                      counter=counter))
+        else:
+            refs.append(sum(u[a] * oracle.tilt(fx, fy, w, cx, cy, D, d, R, R_block, axis=a, K=K,
+                                               seed=seed, counter=counter)
+                            for a in (0, 1) if u[a] != 0.0))
+    return inst, refs
+
+
+@pytest.mark.parametrize("precision", [1, 2, 3])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
+def test_batch_apertures_every_shape(q, ctx, precision, shape):
+    inst, refs = aperture_instances(q)
+    b = q.Batch(ctx, inst, precision=precision)
+    b.set_shape(shape)
+    print(f"apertures shape {shape} p{precision}", flush=True)
+    check(b.execute(), refs, TOL[precision], f"apertures shape {shape} p{precision}")
+    b.close()
+
+
+def test_batch_apertures_graph(q, ctx):
+    inst, refs = aperture_instances(q)
+    b = q.Batch(ctx, inst, precision=3)
+    eager = [o.clone() for o in b.execute()]
+    for rep in range(2):
+        for o in b.outputs:
+            o.fill_(float("nan"))
+        b.execute(use_graph=True)
+        torch.cuda.synchronize()
+        for o, e in zip(b.outputs, eager):
+            assert torch.equal(o, e), rep
+    check(b.outputs, refs, TOL[3], "apertures graph")
+    b.close()
+
+
+def test_batch_rejects_bad_apertures(q, ctx):
+    inst, _ = aperture_instances(q)
+    bad = dict(inst[-1])
+    del bad["apd"]
+    with pytest.raises(q.QrfsError):
+        q.Batch(ctx, [bad], precision=1)
+    bad = dict(inst[0])
+    bad["u"] = (1.0, 0.0)  # a direction without apertures
+    with pytest.raises(q.QrfsError) as e:
+        q.Batch(ctx, [bad], precision=1)
+    assert "apertures" in e.value.detail
