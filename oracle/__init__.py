@@ -58,6 +58,13 @@ def _load():
         "oracle_tilt": (None, [_i64, _p, _p, _p, _i64, _p, _p, _p, _p, _i64, _i64, _u64, _u64,
                                _i32, _p, _i32, _p]),
         "oracle_sample_disc": (None, [_u64, _u64, _u64, _i64, _i64, _d, _p, _p, _p]),
+        "oracle_pseudo_points": (None, [_u64, _u64, _u64, _i64, _p, _p]),
+        "oracle_sample_pseudo": (None, [_i32, _u64, _u64, _u64, _i64, _i64, _i32, _d, _d, _d,
+                                        _p, _p, _p]),
+        "oracle_sample_jitter": (None, [_u64, _u64, _u64, _i64, _i32, _d, _p, _p, _p]),
+        "oracle_point_set_measures": (None, [_i64, _i64, _p, _p, _d, _d, _d, _d, _d, _p, _p,
+                                             _p]),
+        "oracle_set_sf_expectation": (None, [_i64, _p, _p, _p, _i64, _i64, _p, _p, _p]),
         "oracle_choose_cartesian": (_i64, [_i32, _d, _d, _d, _i32, _d, _d, _d, _d, _p]),
         "oracle_temporal_experiment": (None, [_i64, _p, _p, _p, _p, _p, _p, _d, _i64, _i64,
                                               _i64, _u64, _u64, _i32, _p, _p]),
@@ -145,6 +152,59 @@ def sample_disc(n_sets, K, fmax, index=0, s0x=SEED_HALF, s0y=SEED_HALF):
     fx, fy, area = np.zeros(n), np.zeros(n), np.zeros(n)
     _load().oracle_sample_disc(s0x, s0y, index, n_sets, K, fmax, _ptr(fx), _ptr(fy), _ptr(area))
     return fx, fy, area
+
+
+MAP_CARTESIAN, MAP_LOGPOLAR, MAP_DISC = 0, 1, 3
+
+
+def pseudo_points(n, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
+    """Unit-square points index+1 .. index+n of the pseudo-random frequency
+    stream (Philox4x32-10 in its own counter domain)."""
+    ux, uy = np.zeros(n), np.zeros(n)
+    _load().oracle_pseudo_points(seed_x, seed_y, index, n, _ptr(ux), _ptr(uy))
+    return ux, uy
+
+
+def sample_pseudo(map_, n_sets, K, N=0, df=0.0, fmin=0.0, fmax=0.0, index=0, seed_x=SEED_HALF,
+                  seed_y=SEED_HALF):
+    """Fully random frequencies (Sec. 3.1) through the Cartesian (map 0),
+    log-polar (1) or disc (3) map."""
+    n = n_sets * K
+    fx, fy, area = np.zeros(n), np.zeros(n), np.zeros(n)
+    _load().oracle_sample_pseudo(map_, seed_x, seed_y, index, n_sets, K, N, df, fmin, fmax,
+                                 _ptr(fx), _ptr(fy), _ptr(area))
+    return fx, fy, area
+
+
+def sample_jitter(n_sets, N, df, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
+    """Randomly jittered grid of Eq. 4: one point per df x df cell of the
+    N x N grid centred on the origin (K = N^2)."""
+    n = n_sets * N * N
+    fx, fy, area = np.zeros(n), np.zeros(n), np.zeros(n)
+    _load().oracle_sample_jitter(seed_x, seed_y, index, n_sets, N, df, _ptr(fx), _ptr(fy),
+                                 _ptr(area))
+    return fx, fy, area
+
+
+def point_set_measures(fx, fy, n_sets, K, x0, y0, Lx, Ly, r_clash):
+    """Per set: (minimum pairwise distance, pairs closer than r_clash, L2
+    star discrepancy) of the points mapped to the unit square."""
+    fx, fy = _f64(fx), _f64(fy)
+    md, T = np.zeros(n_sets), np.zeros(n_sets)
+    nc = np.zeros(n_sets, dtype=np.int64)
+    _load().oracle_point_set_measures(n_sets, K, _ptr(fx), _ptr(fy), x0, y0, Lx, Ly, r_clash,
+                                      _ptr(md), nc.ctypes.data_as(ctypes.c_void_p), _ptr(T))
+    return md, nc, T
+
+
+def set_sf_expectation(fx, fy, w, n_sets, K, bx, by):
+    """Noise-free differential-piston structure function of each set,
+    [n_sets][nB]: sum_k w_k^2 2 (1 - cos 2 pi f_k.B)."""
+    fx, fy, w, bx, by = map(_f64, (fx, fy, w, bx, by))
+    S = np.zeros((n_sets, bx.size))
+    _load().oracle_set_sf_expectation(K, _ptr(fx), _ptr(fy), _ptr(w), n_sets, bx.size, _ptr(bx),
+                                      _ptr(by), _ptr(S))
+    return S
 
 
 def choose_cartesian(df, eps, r0=0.1, L0=25.0, D=None, d=0.0, c=None, model=PSD_VON_KARMAN):

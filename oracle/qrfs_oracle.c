@@ -92,9 +92,26 @@ ORACLE_API void oracle_r2_points(uint64_t s0x, uint64_t s0y, uint64_t index,
 /* Frequency maps                                                      */
 /* ------------------------------------------------------------------ */
 
-/* Eq. 5 with delta_f_x = delta_f_y = df and n_x = n_y = N (Sec. 3.2):
- * f = df*N*(u - 1/2).  Each of the K points of a set stands for an equal
- * share (N df)^2 / K of the square domain (delta_f^2 when K = N^2, Eq. 3). */
+/* Maps of unit-square points (ux, uy) to frequencies (map 0: Cartesian,
+ * 1: log-polar, 3: disc), K points per set.
+ *
+ * Cartesian, Eq. 5 with delta_f_x = delta_f_y = df and n_x = n_y = N
+ * (Sec. 3.2): f = df*N*(u - 1/2).  Each of the K points of a set stands for
+ * an equal share (N df)^2 / K of the square domain (delta_f^2 when
+ * K = N^2, Eq. 3).
+ *
+ * Log-polar: ln|f| uniform on [ln fmin, ln fmax] from the first coordinate,
+ * angle 2 pi u from the second.  The (ln f, theta) box has measure
+ * 2 pi ln(fmax/fmin); its Jacobian to (fx, fy) is |f|^2, so each of the K
+ * points of a set carries area 2 pi ln(fmax/fmin) |f|^2 / K.
+ *
+ * Disc: polar quasi-random frequencies through the concentric map onto the
+ * disc |f| < fmax; every point stands for the same cell area
+ * pi fmax^2 / K. */
+static void map_points(int32_t map, int64_t n, int64_t K, int32_t N, double df, double fmin,
+                       double fmax, const double* ux, const double* uy, double* fx, double* fy,
+                       double* area);
+
 ORACLE_API void oracle_sample_cartesian(uint64_t s0x, uint64_t s0y, uint64_t index,
                                         int64_t n_sets, int64_t K, int32_t N, double df,
                                         double* fx, double* fy, double* area) {
@@ -102,20 +119,11 @@ ORACLE_API void oracle_sample_cartesian(uint64_t s0x, uint64_t s0y, uint64_t ind
     double* ux = (double*)malloc(sizeof(double) * (size_t)n);
     double* uy = (double*)malloc(sizeof(double) * (size_t)n);
     oracle_r2_points(s0x, s0y, index, n, ux, uy);
-    double L = (double)N * df;
-    for (int64_t i = 0; i < n; ++i) {
-        fx[i] = L * (ux[i] - 0.5);
-        fy[i] = L * (uy[i] - 0.5);
-        area[i] = L * L / (double)K;
-    }
+    map_points(0, n, K, N, df, 0.0, 0.0, ux, uy, fx, fy, area);
     free(ux);
     free(uy);
 }
 
-/* Log-polar map: ln|f| uniform on [ln fmin, ln fmax] from the first R2
- * coordinate, angle 2 pi u from the second.  The (ln f, theta) box has
- * measure 2 pi ln(fmax/fmin); its Jacobian to (fx, fy) is |f|^2, so each of
- * the K points of a set carries area 2 pi ln(fmax/fmin) |f|^2 / K. */
 ORACLE_API void oracle_sample_logpolar(uint64_t s0x, uint64_t s0y, uint64_t index,
                                        int64_t n_sets, int64_t K, double fmin, double fmax,
                                        double* fx, double* fy, double* area) {
@@ -123,14 +131,7 @@ ORACLE_API void oracle_sample_logpolar(uint64_t s0x, uint64_t s0y, uint64_t inde
     double* ux = (double*)malloc(sizeof(double) * (size_t)n);
     double* uy = (double*)malloc(sizeof(double) * (size_t)n);
     oracle_r2_points(s0x, s0y, index, n, ux, uy);
-    double lr = log(fmax / fmin);
-    for (int64_t i = 0; i < n; ++i) {
-        double f = fmin * exp(lr * ux[i]);
-        double th = 2.0 * M_PI * uy[i];
-        fx[i] = f * cos(th);
-        fy[i] = f * sin(th);
-        area[i] = 2.0 * M_PI * lr * f * f / (double)K;
-    }
+    map_points(1, n, K, 0, 0.0, fmin, fmax, ux, uy, fx, fy, area);
     free(ux);
     free(uy);
 }
@@ -157,21 +158,111 @@ ORACLE_API void oracle_concentric_map(double ux, double uy, double* x, double* y
     *y = r * sin(phi);
 }
 
-/* Polar quasi-random frequencies: R2 points through the concentric map onto
- * the disc |f| < fmax; every point stands for the same cell area
- * pi fmax^2 / K. */
 ORACLE_API void oracle_sample_disc(uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n_sets,
                                    int64_t K, double fmax, double* fx, double* fy, double* area) {
     int64_t n = n_sets * K;
     double* ux = (double*)malloc(sizeof(double) * (size_t)n);
     double* uy = (double*)malloc(sizeof(double) * (size_t)n);
     oracle_r2_points(s0x, s0y, index, n, ux, uy);
+    map_points(3, n, K, 0, 0.0, 0.0, fmax, ux, uy, fx, fy, area);
+    free(ux);
+    free(uy);
+}
+
+static void map_points(int32_t map, int64_t n, int64_t K, int32_t N, double df, double fmin,
+                       double fmax, const double* ux, const double* uy, double* fx, double* fy,
+                       double* area) {
+    if (map == 0) {
+        double L = (double)N * df;
+        for (int64_t i = 0; i < n; ++i) {
+            fx[i] = L * (ux[i] - 0.5);
+            fy[i] = L * (uy[i] - 0.5);
+            area[i] = L * L / (double)K;
+        }
+    } else if (map == 1) {
+        double lr = log(fmax / fmin);
+        for (int64_t i = 0; i < n; ++i) {
+            double f = fmin * exp(lr * ux[i]);
+            double th = 2.0 * M_PI * uy[i];
+            fx[i] = f * cos(th);
+            fy[i] = f * sin(th);
+            area[i] = 2.0 * M_PI * lr * f * f / (double)K;
+        }
+    } else {
+        for (int64_t i = 0; i < n; ++i) {
+            double x, y;
+            oracle_concentric_map(ux[i], uy[i], &x, &y);
+            fx[i] = fmax * x;
+            fy[i] = fmax * y;
+            area[i] = M_PI * fmax * fmax / (double)K;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Pseudo-random and jittered frequency sampling (Sec. 3.1, Eq. 4): the  */
+/* randomised schemes the quasi-random sampling is set against         */
+/* ------------------------------------------------------------------ */
+
+ORACLE_API void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                                     uint32_t out[4]);
+
+/* Unit-square point n of the pseudo-random frequency stream: one
+ * Philox4x32-10 block keyed by seed_x, counter (n lo, n hi, low word of
+ * seed_y, 0x46524551); every coefficient counter ends in a zero word, so
+ * the two streams never share a block.  ux is the top 53 bits of words
+ * (1:0) times 2^-53, uy the same of words (3:2), the form of the R2 points.
+ * Points n = index+1 .. index+n_pts, as for the R2 sequence. */
+ORACLE_API void oracle_pseudo_points(uint64_t seed_x, uint64_t seed_y, uint64_t index,
+                                     int64_t n_pts, double* ux, double* uy) {
+    uint32_t key[2] = {(uint32_t)seed_x, (uint32_t)(seed_x >> 32)};
+    for (int64_t i = 0; i < n_pts; ++i) {
+        uint64_t n = index + 1u + (uint64_t)i;
+        uint32_t ctr[4] = {(uint32_t)n, (uint32_t)(n >> 32), (uint32_t)seed_y, 0x46524551u};
+        uint32_t x[4];
+        oracle_philox4x32_10(ctr, key, x);
+        uint64_t a = ((uint64_t)x[1] << 32) | x[0];
+        uint64_t b = ((uint64_t)x[3] << 32) | x[2];
+        ux[i] = (double)(a >> 11) * 0x1p-53;
+        uy[i] = (double)(b >> 11) * 0x1p-53;
+    }
+}
+
+/* Fully random frequencies: the pseudo-random points through map 0, 1 or 3
+ * (the same maps and cell areas as the quasi-random schemes). */
+ORACLE_API void oracle_sample_pseudo(int32_t map, uint64_t seed_x, uint64_t seed_y,
+                                     uint64_t index, int64_t n_sets, int64_t K, int32_t N,
+                                     double df, double fmin, double fmax, double* fx, double* fy,
+                                     double* area) {
+    int64_t n = n_sets * K;
+    double* ux = (double*)malloc(sizeof(double) * (size_t)n);
+    double* uy = (double*)malloc(sizeof(double) * (size_t)n);
+    oracle_pseudo_points(seed_x, seed_y, index, n, ux, uy);
+    map_points(map, n, K, N, df, fmin, fmax, ux, uy, fx, fy, area);
+    free(ux);
+    free(uy);
+}
+
+/* Randomly jittered grid, Eq. 4: the square of side N df centred on the
+ * origin is cut into N x N cells of side df; point k = iy N + ix of a set
+ * lies in cell (ix, iy), at its lower corner f' = -N df / 2 + i df plus
+ * R_u df, written df (i + R_u - N/2).  One point per cell, so K = N^2 and
+ * every point stands for df^2.  R_u: the pseudo-random stream, point
+ * n = index + 1 + s K + k for point k of set s. */
+ORACLE_API void oracle_sample_jitter(uint64_t seed_x, uint64_t seed_y, uint64_t index,
+                                     int64_t n_sets, int32_t N, double df, double* fx,
+                                     double* fy, double* area) {
+    int64_t K = (int64_t)N * N;
+    int64_t n = n_sets * K;
+    double* ux = (double*)malloc(sizeof(double) * (size_t)n);
+    double* uy = (double*)malloc(sizeof(double) * (size_t)n);
+    oracle_pseudo_points(seed_x, seed_y, index, n, ux, uy);
     for (int64_t i = 0; i < n; ++i) {
-        double x, y;
-        oracle_concentric_map(ux[i], uy[i], &x, &y);
-        fx[i] = fmax * x;
-        fy[i] = fmax * y;
-        area[i] = M_PI * fmax * fmax / (double)K;
+        int64_t k = i % K;
+        double ix = (double)(k % N), iy = (double)(k / N);
+        fx[i] = df * (ix + ux[i] - 0.5 * (double)N);
+        fy[i] = df * (iy + uy[i] - 0.5 * (double)N);
+        area[i] = df * df;
     }
     free(ux);
     free(uy);
@@ -860,4 +951,70 @@ ORACLE_API void oracle_sample_learned(uint64_t s0x, uint64_t s0y, uint64_t index
     }
     free(ux);
     free(uy);
+}
+
+/* ------------------------------------------------------------------ */
+/* Point-set measures of frequency sets (Sec. 3.1-3.2: clashes, gaps,   */
+/* discrepancy) and the per-set sampling error                          */
+/* ------------------------------------------------------------------ */
+/* For each set s of K points, mapped to the unit square by
+ * u = ((fx - x0)/Lx, (fy - y0)/Ly):
+ *   min_dist[s]  the smallest distance between two of its points;
+ *   n_clash[s]   the number of pairs closer than r_clash (the frequency
+ *                "clashes" of Sec. 3.1);
+ *   l2_star[s]   the L2 star discrepancy T, from Warnock's closed form
+ *     T^2 = 1/9 - (1/(2K)) sum_i (1 - x_i^2)(1 - y_i^2)
+ *           + (1/K^2) sum_i sum_j (1 - max(x_i, x_j)) (1 - max(y_i, y_j)). */
+ORACLE_API void oracle_point_set_measures(int64_t n_sets, int64_t K, const double* fx,
+                                          const double* fy, double x0, double y0, double Lx,
+                                          double Ly, double r_clash, double* min_dist,
+                                          int64_t* n_clash, double* l2_star) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n_sets; ++s) {
+        const double* px = fx + s * K;
+        const double* py = fy + s * K;
+        double dmin2 = INFINITY, s1 = 0.0, s2 = 0.0;
+        int64_t clash = 0;
+        for (int64_t i = 0; i < K; ++i) {
+            double xi = (px[i] - x0) / Lx, yi = (py[i] - y0) / Ly;
+            s1 += (1.0 - xi * xi) * (1.0 - yi * yi);
+            for (int64_t j = 0; j < K; ++j) {
+                double xj = (px[j] - x0) / Lx, yj = (py[j] - y0) / Ly;
+                s2 += (1.0 - fmax(xi, xj)) * (1.0 - fmax(yi, yj));
+                if (j > i) {
+                    double d2 = (xi - xj) * (xi - xj) + (yi - yj) * (yi - yj);
+                    if (d2 < dmin2) dmin2 = d2;
+                    if (d2 < r_clash * r_clash) ++clash;
+                }
+            }
+        }
+        double Kd = (double)K;
+        double T2 = 1.0 / 9.0 - s1 / (2.0 * Kd) + s2 / (Kd * Kd);
+        min_dist[s] = sqrt(dmin2);
+        n_clash[s] = clash;
+        l2_star[s] = sqrt(T2 > 0.0 ? T2 : 0.0);
+    }
+}
+
+/* Conditional expectation of the differential-piston structure function
+ * given one frequency set (its noise-free value): the coefficients are iid
+ * N(0,1), so p(B) - p(0) is N(0, S) with
+ *   S[s][b] = sum_k w_k^2 2 (1 - cos 2 pi f_k.B_b),
+ * w carrying the aperture filter of Eq. 7.  Its relative error against the
+ * analytic curve is the sampling error of the set alone. */
+ORACLE_API void oracle_set_sf_expectation(int64_t K, const double* fx, const double* fy,
+                                          const double* w, int64_t n_sets, int64_t nB,
+                                          const double* bx, const double* by, double* S) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n_sets; ++s) {
+        for (int64_t b = 0; b < nB; ++b) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < K; ++k) {
+                int64_t i = s * K + k;
+                double arg = 2.0 * M_PI * (fx[i] * bx[b] + fy[i] * by[b]);
+                acc += w[i] * w[i] * 2.0 * (1.0 - cos(arg));
+            }
+            S[s * nB + b] = acc;
+        }
+    }
 }
