@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain-vs-chosen comparison (learned proposal)")
     ap.add_argument("--workload", choices=["diffpiston", "phase", "large_screen", "batched",
-                                           "temporal"],
+                                           "temporal", "sampler_ablation"],
                     default="diffpiston",
                     help="diffpiston: the headline line; the others print their own report")
     return ap.parse_args()
@@ -390,6 +390,76 @@ def workload_temporal(args):
     print(json.dumps(out), flush=True)
 
 
+# FP64 vector ops per unordered pair in k_pair_measures, with 1 - x and
+# 1 - y formed once per point: Warnock term (2 minima, product, sum),
+# squared distance (2 differences, 2 squares, sum), running minimum (1),
+# clash count (compare, add)
+PAIR_OPS = 12
+
+
+def workload_sampler_ablation(args):
+    """The samplers Sec. 3.1-3.2 compares (R2 against the jittered grid of
+    Eq. 4 and fully random frequencies), on the worked example's Cartesian
+    geometry: UTs (D = 8 m, d = 1.1 m), L0 = 22 m, r0 = 0.1 m, df = 0.25/22,
+    N = 44 (K = 1936), 2000 fresh sets each (one per realisation, as the
+    paper draws them).  Per scheme: minimum pairwise distance (in cells),
+    clashes closer than a tenth of a cell, L2 star discrepancy, and the
+    per-set sampling error E_S = RMS over 32 baselines (1-130 m) of the
+    noise-free structure function against its expectation over the square.
+    The pair kernel is timed with events and rated against the FP64 vector
+    peak."""
+    import numpy as np
+    import torch
+    import paper_2404_02978_amd as q
+    from oracle import analytic as A
+    N, df, n_sets = 44, 0.25 / 22, 2000
+    K = N * N
+    D, d, L0, r0 = 8.0, 1.1, 22.0, 0.1
+    B = 10.0 ** np.linspace(0.0, math.log10(130.0), 32)
+    ex = A.diff_piston_sf_square(B, 0.0 * B, r0, L0, D, d, half_width=0.25, n=200)
+    ctx = q.Context(0)
+    dev = torch.device("cuda", 0)
+    bx = torch.as_tensor(B, device=dev)
+    by = torch.zeros_like(bx)
+    L = N * df
+    r_clash = 0.1 / N
+    pair_ops = n_sets * (K * (K - 1) / 2) * PAIR_OPS
+    out = {"workload": "sampler ablation: UTs D=8 m d=1.1 m, L0=22 m, Cartesian N=44 "
+                       "(K=1936), 2000 sets per scheme, 32 baselines 1-130 m",
+           "clash_radius_cells": 0.1, "schemes": {}}
+    samplers = {"r2": lambda: q.cartesian_sampler(N, df),
+                "jitter": lambda: q.jitter_sampler(N, df),
+                "random": lambda: q.random_sampler(q.SAMPLER_RANDOM_CARTESIAN, N=N, df=df)}
+    for name, mk in samplers.items():
+        fx, fy, area = ctx.sample_frequencies(mk(), n_sets, K)
+        w = ctx.weights(q.psd(r0, L0), fx, fy, area, q.Aperture(D, d))
+        t_meas, t_sf = [], []
+        for _ in range(3):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
+            md, nc, T = ctx.point_set_measures(fx, fy, n_sets, K, -L / 2, -L / 2, L, L, r_clash)
+            e[1].record()
+            S = ctx.set_sf_expectation(K, fx, fy, w, n_sets, bx, by)
+            e[2].record()
+            torch.cuda.synchronize()
+            t_meas.append(e[0].elapsed_time(e[1]))
+            t_sf.append(e[1].elapsed_time(e[2]))
+        ms_m, ms_s = sorted(t_meas)[1], sorted(t_sf)[1]
+        S = S.cpu().numpy()
+        es = np.sqrt(np.mean((S / ex[None, :] - 1.0) ** 2, axis=1))
+        out["schemes"][name] = {
+            "min_dist_cells_mean": float(md.mean().item() * N),
+            "min_dist_cells_min": float(md.min().item() * N),
+            "clashes_per_set": float(nc.double().mean().item()),
+            "l2_star_mean": float(T.mean().item()),
+            "E_S_mean": float(es.mean()), "E_S_p95": float(np.percentile(es, 95)),
+            "measures_ms": ms_m, "set_sf_ms": ms_s,
+            "pair_kernel_alu": {"bound": "alu", "achieved": pair_ops / (ms_m * 1e-3) / 1e12,
+                                "peak": VALU_PEAK_TOPS, "unit": "T FP64 ops/s",
+                                "frac": pair_ops / (ms_m * 1e-3) / 1e12 / VALU_PEAK_TOPS}}
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration():
     """A plain 1 GiB device copy: FETCH_SIZE / WRITE_SIZE of this dispatch
     calibrate the HBM byte counters against a known traffic."""
@@ -410,7 +480,8 @@ def main():
         return
     if args.workload != "diffpiston":
         {"phase": workload_phase, "large_screen": workload_large_screen,
-         "batched": workload_batched, "temporal": workload_temporal}[args.workload](args)
+         "batched": workload_batched, "temporal": workload_temporal,
+         "sampler_ablation": workload_sampler_ablation}[args.workload](args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "

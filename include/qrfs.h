@@ -145,17 +145,35 @@ typedef struct {
  *       proposal, u_y through the inverse CDF of its angular factor, and
  *       each point gets the area f^2 / (K q), q the density of the draw, so
  *       the weighted sums stay unbiased.
- * seed_x, seed_y: S0 in 0.64 fixed point (2^63 = 1/2, Sec. 3.2's (0.5, 0.5)).
+ * The randomised schemes that Sec. 3.1 sets the quasi-random sampling
+ * against draw their unit-square points u from a pseudo-random stream
+ * instead: Philox4x32-10 keyed by seed_x, counter (n lo, n hi, low word of
+ * seed_y, 0x46524551) for point n (disjoint from every coefficient
+ * counter, whose last word is 0); u_x = top 53 bits of words (1:0) times
+ * 2^-53, u_y the same of words (3:2).
+ *   RANDOM_CARTESIAN, RANDOM_LOGPOLAR, RANDOM_DISC: fully random
+ *       frequencies through the Cartesian, log-polar and disc maps above
+ *       (same parameters and cell areas).
+ *   JITTER (Eq. 4): the square of side N df centred on the origin is cut
+ *       into N x N cells of side df; point k = iy N + ix of a set lies in
+ *       cell (ix, iy) at df (i + u - N/2) per axis, area df^2.  K must
+ *       equal N^2.
+ * seed_x, seed_y: R2 schemes: S0 in 0.64 fixed point (2^63 = 1/2,
+ * Sec. 3.2's (0.5, 0.5)); randomised schemes: key and stream id as above.
  * index (IN/OUT): position in the sequence; every call advances it by the
  * number of points drawn, so consecutive calls continue the sequence. */
 #define QRFS_SAMPLER_R2_CARTESIAN 0
 #define QRFS_SAMPLER_R2_LOGPOLAR 1
 #define QRFS_SAMPLER_LEARNED 2
 #define QRFS_SAMPLER_R2_DISC 3
+#define QRFS_SAMPLER_JITTER 4
+#define QRFS_SAMPLER_RANDOM_CARTESIAN 5
+#define QRFS_SAMPLER_RANDOM_LOGPOLAR 6
+#define QRFS_SAMPLER_RANDOM_DISC 7
 typedef struct {
     int32_t scheme;
-    int32_t N;   /* Cartesian: points per axis of the domain (> 0)   */
-    double df;   /* Cartesian: frequency pitch (> 0)                 */
+    int32_t N;   /* Cartesian, jitter: points per axis (> 0)        */
+    double df;   /* Cartesian, jitter: frequency pitch (> 0)         */
     double fmin; /* log-polar: band, 0 < fmin < fmax                 */
     double fmax; /* log-polar: upper band edge; disc: radius (> 0)   */
     uint64_t seed_x;
@@ -348,6 +366,47 @@ QRFS_API qrfs_status qrfs_temporal_piston_structure(
     const double* c2, const double* v, double dt, int64_t M, qrfs_sampler* s, int64_t K,
     int64_t R, int64_t R_block, const qrfs_rng* rng, int32_t precision, double* sf,
     double* sf_stderr, void* stream);
+
+/* --------------------------------------------------- sampler comparison */
+/* Point-set measures of frequency sets, the properties Sec. 3.1-3.2 weigh
+ * the samplers by: frequencies that "clash" (fall almost on top of each
+ * other), gaps, and even coverage.  Set s is fx, fy [s*K, (s+1)*K), mapped
+ * to the unit square by u = ((fx - x0)/Lx, (fy - y0)/Ly) (for the Cartesian
+ * and jittered schemes x0 = y0 = -N df/2, Lx = Ly = N df).  Per set:
+ *   min_dist[s]  smallest distance |u_i - u_j| over its pairs (+inf for K=1),
+ *   n_clash[s]   number of pairs with |u_i - u_j| < r_clash,
+ *   l2_star[s]   L2 star discrepancy T of the points in [0,1]^2 (Warnock):
+ *     T^2 = 1/9 - (1/(2K)) sum_i (1 - x_i^2)(1 - y_i^2)
+ *           + (1/K^2) sum_{i,j} (1 - max(x_i, x_j)) (1 - max(y_i, y_j)).
+ * Distances are formed in FP64 without fused multiply-adds, so min_dist and
+ * n_clash are those of the plain definition exactly; the sums run in FP64
+ * in a fixed order (bit-reproducible).  O(K^2) work per set.
+ * fx, fy: device double[n_sets*K]; min_dist, l2_star: device double[n_sets];
+ * n_clash: device int64[n_sets].  Uses the context's workspace.
+ * Errors: n_sets, K < 1; K > 2^24; n_sets * ceil(K/256) >= 2^31; Lx, Ly not
+ * > 0 or x0, y0 not finite; r_clash < 0; NULL or misaligned arrays. */
+QRFS_API qrfs_status qrfs_point_set_measures(qrfs_context* ctx, int64_t n_sets, int64_t K,
+                                             const double* fx, const double* fy, double x0,
+                                             double y0, double Lx, double Ly, double r_clash,
+                                             double* min_dist, int64_t* n_clash, double* l2_star,
+                                             void* stream);
+
+/* Noise-free differential-piston structure function of each frequency set:
+ * given the set, the coefficients are iid N(0, 1), so p(B) - p(0) is
+ * N(0, S) with
+ *   S[s][b] = sum_k w_k^2 2 (1 - cos 2 pi f_k.B_b)
+ * (w carrying the aperture filter of Eq. 7, as qrfs_weights gives it with
+ * an aperture).  Its relative error against the analytic curve is the
+ * sampling error of the set alone (no coefficient noise), the quantity the
+ * samplers are compared on.  Formed as w^2 4 sin^2(pi r), r = f.B reduced
+ * to [-1/2, 1/2] in FP64; FP64 sums in a fixed order.
+ * fx, fy, w: device double[n_sets*K]; bx, by: device double[nB];
+ * S: device double[n_sets][nB].
+ * Errors: K, n_sets, nB < 1; n_sets >= 2^31; NULL or misaligned arrays. */
+QRFS_API qrfs_status qrfs_set_sf_expectation(qrfs_context* ctx, int64_t K, const double* fx,
+                                             const double* fy, const double* w, int64_t n_sets,
+                                             int64_t nB, const double* bx, const double* by,
+                                             double* S, void* stream);
 
 /* ------------------------------------------------------ learned proposal */
 /* A proposal density for the frequency sampler, learned from the variance

@@ -162,6 +162,17 @@ def temporal_sf(tau, B, v, r0, L0, D, d=0.0, c=None, model=1, fmin=1e-7, fmax=No
     return np.array(out)
 
 
+def _square_rule(half_width, n):
+    """Nodes and weights of a tensor Gauss-Legendre rule on n x n panels of
+    the square [-half_width, half_width)^2 (6 points per panel and axis)."""
+    xg, wg = np.polynomial.legendre.leggauss(6)
+    edges = np.linspace(-half_width, half_width, n + 1)
+    h = np.diff(edges)
+    nodes = (edges[:-1, None] + 0.5 * h[:, None] * (xg[None, :] + 1.0)).ravel()
+    wts = (0.5 * h[:, None] * wg[None, :]).ravel()
+    return nodes, wts
+
+
 def temporal_sf_square(tau, B, v, r0, L0, D, d=0.0, half_width=0.25, c=None, model=1, n=801):
     """Exact expectation of the temporal estimator when the frequencies fill
     the square [-half_width, half_width)^2 (the Cartesian R2 domain of Eq. 5,
@@ -172,14 +183,9 @@ def temporal_sf_square(tau, B, v, r0, L0, D, d=0.0, half_width=0.25, c=None, mod
     B = np.asarray(B, dtype=float)
     v = np.asarray(v, dtype=float)
     tau = np.atleast_1d(np.asarray(tau, dtype=float))
-    # n x n panels of a 6-point rule, summed one strip of rows at a time
-    xg, wg = np.polynomial.legendre.leggauss(6)
-    edges = np.linspace(-half_width, half_width, n + 1)
-    h = np.diff(edges)
-    nodes = (edges[:-1, None] + 0.5 * h[:, None] * (xg[None, :] + 1.0)).ravel()
-    wts = (0.5 * h[:, None] * wg[None, :]).ravel()
+    nodes, wts = _square_rule(half_width, n)
     out = np.zeros(tau.size)
-    step = 256
+    step = 256  # one strip of rows at a time
     for i0 in range(0, nodes.size, step):
         FX, FY = np.meshgrid(nodes[i0:i0 + step], nodes, indexing="ij")
         WW = np.outer(wts[i0:i0 + step], wts)
@@ -189,6 +195,27 @@ def temporal_sf_square(tau, B, v, r0, L0, D, d=0.0, half_width=0.25, c=None, mod
         for j, t in enumerate(tau):
             u = v * t
             out[j] += 16.0 * np.sum(base * np.sin(np.pi * (FX * u[0] + FY * u[1])) ** 2)
+    return out
+
+
+def diff_piston_sf_square(Bx, By, r0, L0, D, d=0.0, half_width=0.25, c=None, model=1, n=401):
+    """Expectation of the differential-piston structure function when the
+    frequencies fill the square [-half_width, half_width)^2: the double
+    integral of W F^2 2 (1 - cos 2 pi f.B) = W F^2 4 sin^2(pi f.B) over the
+    square, by the same tensor Gauss-Legendre rule."""
+    c = psd_constant() if c is None else c
+    Bx = np.atleast_1d(np.asarray(Bx, dtype=float))
+    By = np.atleast_1d(np.asarray(By, dtype=float))
+    nodes, wts = _square_rule(half_width, n)
+    out = np.zeros(Bx.size)
+    step = 256
+    for i0 in range(0, nodes.size, step):
+        FX, FY = np.meshgrid(nodes[i0:i0 + step], nodes, indexing="ij")
+        WW = np.outer(wts[i0:i0 + step], wts)
+        f = np.maximum(np.hypot(FX, FY), 1e-300)
+        base = WW * _psd(f, r0, L0, c, model) * aperture_filter(f, D, d) ** 2
+        for j in range(Bx.size):
+            out[j] += 4.0 * np.sum(base * np.sin(np.pi * (FX * Bx[j] + FY * By[j])) ** 2)
     return out
 
 

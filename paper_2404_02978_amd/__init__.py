@@ -28,6 +28,10 @@ SAMPLER_R2_CARTESIAN = 0
 SAMPLER_R2_LOGPOLAR = 1
 SAMPLER_LEARNED = 2
 SAMPLER_R2_DISC = 3
+SAMPLER_JITTER = 4
+SAMPLER_RANDOM_CARTESIAN = 5
+SAMPLER_RANDOM_LOGPOLAR = 6
+SAMPLER_RANDOM_DISC = 7
 COEF_GAUSS_CS = 0
 COEF_EQ3 = 1
 PREC_FP64 = 0
@@ -103,6 +107,19 @@ def cartesian_sampler(N, df, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
     return Sampler(SAMPLER_R2_CARTESIAN, N, df, 0.0, 0.0, seed_x, seed_y, index, None)
 
 
+def jitter_sampler(N, df, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
+    """Randomly jittered grid of Eq. 4 (K must be N^2); seed_x is the
+    Philox key, the low word of seed_y the stream id."""
+    return Sampler(SAMPLER_JITTER, N, df, 0.0, 0.0, seed_x, seed_y, index, None)
+
+
+def random_sampler(scheme, N=0, df=0.0, fmin=0.0, fmax=0.0, index=0, seed_x=SEED_HALF,
+                   seed_y=SEED_HALF):
+    """Fully random frequencies (Sec. 3.1) through the Cartesian, log-polar
+    or disc map: scheme SAMPLER_RANDOM_CARTESIAN / _LOGPOLAR / _DISC."""
+    return Sampler(scheme, N, df, fmin, fmax, seed_x, seed_y, index, None)
+
+
 def learned_sampler(proposal, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
     """R2 points warped through the sampling table of `proposal`."""
     return Sampler(SAMPLER_LEARNED, 0, 0.0, proposal.fmin, proposal.fmax, seed_x, seed_y, index,
@@ -163,6 +180,10 @@ def load_library():
                                            _P, _P, ctypes.POINTER(Sampler), _I64, _I64, _I64,
                                            ctypes.POINTER(Rng), _I32, _P, _P, _P]),
         "qrfs_temporal_sf": (S, [_P, _I64, _I64, _I32, _P, _P, _P, _P]),
+        "qrfs_point_set_measures": (S, [_P, _I64, _I64, _P, _P, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, _P, _P, _P, _P]),
+        "qrfs_set_sf_expectation": (S, [_P, _I64, _P, _P, _P, _I64, _I64, _P, _P, _P, _P]),
         "qrfs_temporal_piston_structure": (
             S, [_P, ctypes.POINTER(Psd), ctypes.POINTER(Aperture), ctypes.POINTER(ctypes.c_double),
                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_double,
@@ -366,6 +387,30 @@ class Context:
             _dev_f64(by, "by", nB), ctypes.byref(sampler), K, R, R_block, ctypes.byref(rng),
             precision, _ptr(sf), _ptr(se), _stream()))
         return sf, se
+
+    def point_set_measures(self, fx, fy, n_sets, K, x0, y0, Lx, Ly, r_clash):
+        """Per set: minimum pairwise distance, clash count and L2 star
+        discrepancy of the points mapped to the unit square (device
+        tensors: float64, int64, float64 [n_sets])."""
+        md = torch.empty(n_sets, dtype=torch.float64, device=self.device)
+        nc = torch.empty(n_sets, dtype=torch.int64, device=self.device)
+        T = torch.empty_like(md)
+        _check(load_library().qrfs_point_set_measures(
+            self._h, n_sets, K, _dev_f64(fx, "fx", n_sets * K), _dev_f64(fy, "fy", n_sets * K),
+            float(x0), float(y0), float(Lx), float(Ly), float(r_clash), _ptr(md), _ptr(nc),
+            _ptr(T), _stream()))
+        return md, nc, T
+
+    def set_sf_expectation(self, K, fx, fy, w, n_sets, bx, by):
+        """Noise-free differential-piston structure function of each set,
+        float64 [n_sets][nB] on the device."""
+        nB = bx.numel()
+        S = torch.empty((n_sets, nB), dtype=torch.float64, device=self.device)
+        _check(load_library().qrfs_set_sf_expectation(
+            self._h, K, _dev_f64(fx, "fx", n_sets * K), _dev_f64(fy, "fy", n_sets * K),
+            _dev_f64(w, "w", n_sets * K), n_sets, nB, _dev_f64(bx, "bx"), _dev_f64(by, "by", nB),
+            _ptr(S), _stream()))
+        return S
 
     def temporal_sf(self, pistons, with_stderr=True):
         """Time-lag structure function of the differential piston (Sec. 4.4)

@@ -112,22 +112,27 @@ qrfs_status check_ap(const qrfs_aperture* ap) {
     return QRFS_OK;
 }
 
-qrfs_status check_sampler(const qrfs_sampler* s) {
+qrfs_status check_sampler(const qrfs_sampler* s, int64_t K) {
     if (!s) return fail(QRFS_ERR_INVALID_ARG, "sampler is NULL");
-    if (s->scheme == QRFS_SAMPLER_LEARNED) return qrfs::proposal_check_ready(s->proposal);
-    if (s->scheme == QRFS_SAMPLER_R2_CARTESIAN) {
+    const int sc = s->scheme;
+    if (sc == QRFS_SAMPLER_LEARNED) return qrfs::proposal_check_ready(s->proposal);
+    if (sc == QRFS_SAMPLER_R2_CARTESIAN || sc == QRFS_SAMPLER_RANDOM_CARTESIAN ||
+        sc == QRFS_SAMPLER_JITTER) {
         if (s->N <= 0) return fail(QRFS_ERR_INVALID_ARG, "Cartesian N must be > 0 (got %d)", s->N);
         if (!(s->df > 0.0) || !std::isfinite(s->df))
             return fail(QRFS_ERR_INVALID_ARG, "Cartesian df must be > 0 (got %g)", s->df);
-    } else if (s->scheme == QRFS_SAMPLER_R2_LOGPOLAR) {
+        if (sc == QRFS_SAMPLER_JITTER && K != (int64_t)s->N * s->N)
+            return fail(QRFS_ERR_INVALID_ARG, "jittered grid needs K = N^2 (K=%lld, N=%d)",
+                        (long long)K, s->N);
+    } else if (sc == QRFS_SAMPLER_R2_LOGPOLAR || sc == QRFS_SAMPLER_RANDOM_LOGPOLAR) {
         if (!(s->fmin > 0.0) || !(s->fmax > s->fmin) || !std::isfinite(s->fmax))
             return fail(QRFS_ERR_INVALID_ARG, "log-polar band needs 0 < fmin < fmax (got %g, %g)",
                         s->fmin, s->fmax);
-    } else if (s->scheme == QRFS_SAMPLER_R2_DISC) {
+    } else if (sc == QRFS_SAMPLER_R2_DISC || sc == QRFS_SAMPLER_RANDOM_DISC) {
         if (!(s->fmax > 0.0) || !std::isfinite(s->fmax))
             return fail(QRFS_ERR_INVALID_ARG, "disc radius fmax must be > 0 (got %g)", s->fmax);
     } else {
-        return fail(QRFS_ERR_INVALID_ARG, "unknown sampler scheme %d", s->scheme);
+        return fail(QRFS_ERR_INVALID_ARG, "unknown sampler scheme %d", sc);
     }
     return QRFS_OK;
 }
@@ -419,7 +424,7 @@ qrfs_status qrfs_context_destroy(qrfs_context* ctx) {
 qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s, int64_t n_sets,
                                     int64_t K, double* fx, double* fy, double* area,
                                     void* stream) {
-    qrfs_status st = check_sampler(s);
+    qrfs_status st = check_sampler(s, K);
     if (st) return st;
     if (K <= 0 || n_sets <= 0)
         return fail(QRFS_ERR_INVALID_ARG, "K and n_sets must be > 0 (got %lld, %lld)",
@@ -507,7 +512,7 @@ qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
     if (st) return st;
     if (!ap) return fail(QRFS_ERR_INVALID_ARG, "aperture is required");
     if ((st = check_ap(ap))) return st;
-    if ((st = check_sampler(s))) return st;
+    if ((st = check_sampler(s, K))) return st;
     if ((st = check_sum_common(K, nB, R, R_block, rng, nullptr, precision))) return st;
     CHECK_PTR(bx);
     CHECK_PTR(by);
@@ -585,6 +590,61 @@ qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
     return ok();
 }
 
+qrfs_status qrfs_point_set_measures(qrfs_context* ctx, int64_t n_sets, int64_t K,
+                                    const double* fx, const double* fy, double x0, double y0,
+                                    double Lx, double Ly, double r_clash, double* min_dist,
+                                    int64_t* n_clash, double* l2_star, void* stream) {
+    if (n_sets < 1 || K < 1)
+        return fail(QRFS_ERR_INVALID_ARG, "n_sets and K must be >= 1 (got %lld, %lld)",
+                    (long long)n_sets, (long long)K);
+    if (K > ((int64_t)1 << 24))
+        return fail(QRFS_ERR_INVALID_ARG, "K must be <= 2^24 (got %lld)", (long long)K);
+    if (n_sets * qrfs::measure_tiles(K) >= ((int64_t)1 << 31))
+        return fail(QRFS_ERR_INVALID_ARG, "n_sets * ceil(K/256) must be < 2^31");
+    if (!(Lx > 0.0) || !(Ly > 0.0) || !std::isfinite(Lx) || !std::isfinite(Ly) ||
+        !std::isfinite(x0) || !std::isfinite(y0))
+        return fail(QRFS_ERR_INVALID_ARG, "the unit-square map needs finite x0, y0 and Lx, Ly > 0");
+    if (!(r_clash >= 0.0) || !std::isfinite(r_clash))
+        return fail(QRFS_ERR_INVALID_ARG, "r_clash must be finite and >= 0 (got %g)", r_clash);
+    CHECK_PTR(fx);
+    CHECK_PTR(fy);
+    CHECK_PTR(min_dist);
+    CHECK_PTR(n_clash);
+    CHECK_PTR(l2_star);
+    if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
+    const size_t part_bytes = align256((size_t)(n_sets * qrfs::measure_tiles(K)) * 4 * sizeof(double));
+    qrfs_status st = ensure_workspace(ctx, part_bytes);
+    if (st) return st;
+    hipError_t e = qrfs::launch_point_set_measures(n_sets, K, fx, fy, x0, y0, Lx, Ly, r_clash,
+                                                   (double*)ctx->ws, min_dist, n_clash, l2_star,
+                                                   (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "point-set measure launch");
+    return ok();
+}
+
+qrfs_status qrfs_set_sf_expectation(qrfs_context* ctx, int64_t K, const double* fx,
+                                    const double* fy, const double* w, int64_t n_sets, int64_t nB,
+                                    const double* bx, const double* by, double* S, void* stream) {
+    if (K < 1 || n_sets < 1 || nB < 1)
+        return fail(QRFS_ERR_INVALID_ARG, "K, n_sets and nB must be >= 1");
+    if (n_sets >= ((int64_t)1 << 31))
+        return fail(QRFS_ERR_INVALID_ARG, "n_sets must be < 2^31");
+    CHECK_PTR(fx);
+    CHECK_PTR(fy);
+    CHECK_PTR(w);
+    CHECK_PTR(bx);
+    CHECK_PTR(by);
+    CHECK_PTR(S);
+    if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
+    hipError_t e = qrfs::launch_set_sf(n_sets, K, fx, fy, w, nB, bx, by, S, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "per-set structure function launch");
+    return ok();
+}
+
 qrfs_status qrfs_temporal_sf(qrfs_context* ctx, int64_t R, int64_t M, int32_t precision,
                              const void* pistons, double* sf, double* sf_stderr, void* stream) {
     if (R < 1) return fail(QRFS_ERR_INVALID_ARG, "R must be >= 1 (got %lld)", (long long)R);
@@ -627,7 +687,7 @@ qrfs_status qrfs_temporal_piston_structure(qrfs_context* ctx, const qrfs_psd* ps
     if (st) return st;
     if (!ap) return fail(QRFS_ERR_INVALID_ARG, "aperture is required");
     if ((st = check_ap(ap))) return st;
-    if ((st = check_sampler(s))) return st;
+    if ((st = check_sampler(s, K))) return st;
     if (M < 1 || M > qrfs::TEMPORAL_MAX_M)
         return fail(QRFS_ERR_INVALID_ARG, "M must be in [1, %d] (got %lld)", qrfs::TEMPORAL_MAX_M,
                     (long long)M);

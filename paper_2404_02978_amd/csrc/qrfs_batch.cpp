@@ -88,15 +88,20 @@ qrfs_status check_instance(const qrfs_batch_instance& in, int64_t i) {
     if (!(p.r0 > 0.0) || (p.model == QRFS_PSD_VON_KARMAN && !(p.L0 > 0.0)))
         return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: r0 and L0 must be > 0", (long long)i);
     const qrfs_sampler& s = in.sampler;
-    if (s.scheme == QRFS_SAMPLER_R2_CARTESIAN) {
+    const int sc = s.scheme;
+    if (sc == QRFS_SAMPLER_R2_CARTESIAN || sc == QRFS_SAMPLER_RANDOM_CARTESIAN ||
+        sc == QRFS_SAMPLER_JITTER) {
         if (s.N <= 0 || !(s.df > 0.0))
             return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: Cartesian N, df must be > 0",
                             (long long)i);
-    } else if (s.scheme == QRFS_SAMPLER_R2_LOGPOLAR) {
+        if (sc == QRFS_SAMPLER_JITTER && in.K != (int64_t)s.N * s.N)
+            return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: jittered grid needs K = N^2",
+                            (long long)i);
+    } else if (sc == QRFS_SAMPLER_R2_LOGPOLAR || sc == QRFS_SAMPLER_RANDOM_LOGPOLAR) {
         if (!(s.fmin > 0.0) || !(s.fmax > s.fmin))
             return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: needs 0 < fmin < fmax",
                             (long long)i);
-    } else if (s.scheme == QRFS_SAMPLER_R2_DISC) {
+    } else if (sc == QRFS_SAMPLER_R2_DISC || sc == QRFS_SAMPLER_RANDOM_DISC) {
         if (!(s.fmax > 0.0))
             return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: needs fmax > 0", (long long)i);
     } else {

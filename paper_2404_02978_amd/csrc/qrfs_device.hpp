@@ -60,6 +60,21 @@ __device__ __forceinline__ U32x4 coef_block(uint64_t seed, uint64_t real, uint32
                          (uint32_t)(seed >> 32));
 }
 
+// Unit-square point n of the pseudo-random frequency stream (the randomised
+// samplers of Sec. 3.1): one block keyed by seed_x with counter
+// (n lo, n hi, low word of seed_y, 0x46524551).  Coefficient counters end
+// in a zero word, so the two streams never share a block.  Each coordinate
+// is the top 53 bits of a word pair ((y:x) and (w:z)) times 2^-53.
+__device__ __forceinline__ void pseudo_point(uint64_t seed_x, uint64_t seed_y, uint64_t n,
+                                             double& ux, double& uy) {
+    const U32x4 r = philox4x32_10((uint32_t)n, (uint32_t)(n >> 32), (uint32_t)seed_y,
+                                  0x46524551u, (uint32_t)seed_x, (uint32_t)(seed_x >> 32));
+    const uint64_t a = ((uint64_t)r.y << 32) | r.x;
+    const uint64_t b = ((uint64_t)r.w << 32) | r.z;
+    ux = (double)(a >> 11) * 0x1p-53;
+    uy = (double)(b >> 11) * 0x1p-53;
+}
+
 // 32-bit word -> (2m+1) 2^-24 with m = x >> 9: exact in binary32, in (0,1).
 __device__ __forceinline__ float word_uniform_f32(uint32_t x) {
     return (float)(x >> 9) * 0x1p-23f + 0x1p-24f;

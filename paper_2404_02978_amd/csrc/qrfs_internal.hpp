@@ -125,6 +125,17 @@ hipError_t launch_wide_batch(int precision, bool has_ap, const WideArgs* inst,
                              hipStream_t st);
 hipError_t launch_reset_counter(unsigned* counter, hipStream_t st);
 
+// Point-set measures (qrfs_measures.hip): per set, `part` holds
+// measure_tiles(K) * 4 doubles of partial results.
+int64_t measure_tiles(int64_t K);
+hipError_t launch_point_set_measures(int64_t n_sets, int64_t K, const double* fx,
+                                     const double* fy, double x0, double y0, double Lx, double Ly,
+                                     double r_clash, double* part, double* min_dist,
+                                     int64_t* n_clash, double* l2_star, hipStream_t st);
+hipError_t launch_set_sf(int64_t n_sets, int64_t K, const double* fx, const double* fy,
+                         const double* w, int64_t nB, const double* bx, const double* by,
+                         double* S, hipStream_t st);
+
 // squares of the K-range partial sums, summed per column over blocks of
 // rows: partial[ceil(R/256)][P][2]
 hipError_t launch_sfsum_rows(const float* phi, int ksplit, int64_t R, int64_t P, double* partial,

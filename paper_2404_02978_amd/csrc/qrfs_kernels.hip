@@ -11,20 +11,37 @@ namespace qrfs {
 
 // ------------------------------------------------------------- sampler ----
 // One thread per frequency.  Point n = index + 1 + i of the R2 sequence
-// (Sec. 3.2, Eq. 6), mapped by Eq. 5 (Cartesian, scheme 0), the log-polar
-// map (1) or the square-to-disc map (3).
+// (Sec. 3.2, Eq. 6) for schemes 0, 1, 3, of the pseudo-random stream for
+// schemes 4-7 (the randomised samplers of Sec. 3.1), mapped by Eq. 5
+// (Cartesian: schemes 0, 5), the log-polar map (1, 6), the square-to-disc
+// map (3, 7), or placed in its cell of the jittered grid of Eq. 4 (4).
 __global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n,
-                         int64_t K, double L, double fmin, double lr, double* __restrict__ fx,
-                         double* __restrict__ fy, double* __restrict__ area) {
+                         int64_t K, int32_t N, double df, double L, double fmin, double lr,
+                         double* __restrict__ fx, double* __restrict__ fy,
+                         double* __restrict__ area) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double ux, uy;
-    r2_point(s0x, s0y, index + 1u + (uint64_t)i, ux, uy);
-    if (scheme == 0) {
+    if (scheme >= 4)
+        pseudo_point(s0x, s0y, index + 1u + (uint64_t)i, ux, uy);
+    else
+        r2_point(s0x, s0y, index + 1u + (uint64_t)i, ux, uy);
+    const int map = scheme >= 5 ? (scheme == 7 ? 3 : scheme - 5) : scheme;
+    if (map == 0) {
         fx[i] = L * (ux - 0.5);
         fy[i] = L * (uy - 0.5);
         area[i] = L * L / (double)K;
-    } else if (scheme == 3) {
+    } else if (map == 4) {
+        // Eq. 4: point k = iy N + ix of a set (K = N^2) at its cell's lower
+        // corner -N df / 2 + i df plus the jitter u df, as df (i + u - N/2)
+        // (no product feeds a sum, so nothing is fused)
+        const int64_t k = i % K;
+        const double ix = (double)(k % N), iy = (double)(k / N);
+        const double h = 0.5 * (double)N;
+        fx[i] = df * (ix + ux - h);
+        fy[i] = df * (iy + uy - h);
+        area[i] = df * df;
+    } else if (map == 3) {
         // polar quasi-random frequencies (Sec. 3.2): concentric square-to-
         // disc map of the point, disc radius L, equal cell areas
         const double a = 2.0 * ux - 1.0, b = 2.0 * uy - 1.0;
@@ -725,10 +742,10 @@ hipError_t launch_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
                          int64_t K, int32_t N, double df, double fmin, double fmax, double* fx,
                          double* fy, double* area, hipStream_t st) {
     int64_t n = n_sets * K;
-    double L = scheme == 3 ? fmax : (double)N * df;
-    double lr = scheme == 1 ? log(fmax / fmin) : 0.0;
+    double L = (scheme == 3 || scheme == 7) ? fmax : (double)N * df;
+    double lr = (scheme == 1 || scheme == 6) ? log(fmax / fmin) : 0.0;
     hipLaunchKernelGGL(k_sample, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, scheme, s0x, s0y,
-                       index, n, K, L, fmin, lr, fx, fy, area);
+                       index, n, K, N, df, L, fmin, lr, fx, fy, area);
     return hipGetLastError();
 }
 

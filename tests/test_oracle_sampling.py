@@ -225,3 +225,13 @@ def test_set_sf_expectation_approaches_the_analytic_curve():
     e = S / ref - 1
     print("rel err", np.round(e, 5))
     assert np.max(np.abs(e)) < 2e-3
+
+
+def test_square_expectation_matches_isotropic_curve():
+    """The square-domain integral of W F^2 4 sin^2(pi f.B) (2-D tensor
+    quadrature) reaches the isotropic differential-piston curve (1-D Bessel
+    form) once the square covers the band the UT filter passes."""
+    B = np.array([5.0, 56.5, 130.0])
+    sq = A.diff_piston_sf_square(B, 0 * B, 0.1, 22.0, 8.0, 1.1, half_width=2.0, n=600)
+    full = A.diff_piston_sf(B, 0.1, 22.0, 8.0, 1.1)
+    assert np.max(np.abs(sq / full - 1)) < 1e-6
