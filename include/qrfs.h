@@ -195,8 +195,12 @@ typedef struct {
  *               FP64 accumulation (vector ALU); output double.
  *   FP32        FP64 range reduction of 2 pi f.x, FP32 sincos and
  *               Box-Muller, FP32 matrix-core (MFMA) contraction with FP32
- *               accumulation, promoted to FP64 every 64 frequencies;
- *               output float.
+ *               accumulation, folded into a second FP32 accumulator every
+ *               64 frequencies (the two-phase kernel for wide point sets
+ *               adds into the output every 2048); output float.
+ *   (All FP32-class precisions sum sets of at most 8 realisations on the
+ *   vector ALU with this FP32 arithmetic: a matrix-core tile needs 32 rows.
+ *   The split-BF16 and BF16x6 results are then those FP32 sums.)
  *   SPLIT_BF16  as FP32 but each operand is split into bf16 hi + lo and the
  *               contraction is hi.hi + hi.lo + lo.hi on bf16 MFMA with FP32
  *               accumulation (~16 significant bits); output float.

@@ -250,6 +250,106 @@ __global__ __launch_bounds__(256) void k_sum_f64(SumArgs a, int64_t row_tiles,
     }
 }
 
+// ------------------------------------------- FP64, narrow frequency sets ----
+// Sets of at most 8 realisations (the paper draws fresh frequencies for
+// every realisation: R_block = 1): one point per thread, RB rows per block.
+// Per chunk of 64 frequencies the block stages fx, fy, w and the RB rows'
+// coefficients in LDS (drawn once per block); each thread evaluates its
+// point's basis once per frequency and adds it into its RB rows, in the
+// same order and with the same fused products as k_sum_f64.  A 32-row tile
+// would spend most of its contraction on rows the set does not have.
+constexpr int F64N_KC = 64;
+
+template <int BASIS, int RB>
+__global__ __launch_bounds__(256) void k_sum_f64n(SumArgs a, int64_t col_tiles) {
+    __shared__ double sfx[F64N_KC], sfy[F64N_KC], sw[F64N_KC];
+    __shared__ double sC[RB][2 * F64N_KC];
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    const int64_t ct = (int64_t)blockIdx.x % col_tiles;
+    const int64_t sl = (int64_t)blockIdx.x / col_tiles;
+    const int64_t set = a.set0 + sl;
+    const int64_t row_begin = set * a.R_block;
+    const int64_t set_end = (set + 1) * a.R_block < a.R ? (set + 1) * a.R_block : a.R;
+    const int64_t row_end = row_begin + RB < set_end ? row_begin + RB : set_end;
+    const int64_t p = ct * nt + tid;
+    const bool pok = p < a.P;
+    const double px = pok ? a.px[p] : 0.0;
+    const double py = pok ? a.py[p] : 0.0;
+    double pD = 1.0, pd = 0.0;
+    if (BASIS == BASIS_PISTON && pok) {
+        pD = a.apD[p];
+        pd = a.apd[p];
+    }
+    const double* fx = a.fx + sl * a.K;
+    const double* fy = a.fy + sl * a.K;
+    const double* w = a.w + sl * a.K;
+    const int64_t twoK = 2 * a.K;
+    double acc[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = 0.0;
+
+    for (int64_t k0 = 0; k0 < a.K; k0 += F64N_KC) {
+        __syncthreads();
+        if (tid < F64N_KC) {
+            const int64_t k = k0 + tid;
+            const bool ok = k < a.K;
+            sfx[tid] = ok ? fx[k] : 0.0;
+            sfy[tid] = ok ? fy[k] : 0.0;
+            sw[tid] = ok ? w[k] : 0.0;
+        }
+        // RB rows x 32 Philox blocks (4 coefficients each)
+        for (int i = tid; i < RB * (F64N_KC / 2); i += nt) {
+            const int rr = i / (F64N_KC / 2);
+            const int bt = i % (F64N_KC / 2);
+            const int64_t r = row_begin + rr;
+            double g[4] = {0.0, 0.0, 0.0, 0.0};
+            if (r < row_end) {
+                if (a.coef) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t j = 2 * k0 + 4 * bt + q;
+                        g[q] = j < twoK ? a.coef[r * twoK + j] : 0.0;
+                    }
+                } else {
+                    coef4_f64(a.seed, a.counter + (uint64_t)r, (uint32_t)(k0 / 2 + bt), a.mode, g);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sC[rr][4 * bt + q] = g[q];
+        }
+        __syncthreads();
+        const int nk = a.K - k0 < F64N_KC ? (int)(a.K - k0) : F64N_KC;
+        for (int kk = 0; kk < nk; ++kk) {
+            double t = sfx[kk] * px + sfy[kk] * py;
+            if (BASIS == BASIS_PISTON) t += grad_shift(a.grad);
+            const double rf = frac_centered(t);
+            double sv, cv;
+            if (BASIS == BASIS_DIFF) {
+                const double sh = sinpi(rf);
+                cv = -2.0 * sh * sh;
+                sv = sinpi(2.0 * rf);
+            } else {
+                sincospi(2.0 * rf, &sv, &cv);
+            }
+            double amp = sw[kk];
+            if (BASIS == BASIS_PISTON)
+                amp *= aperture_filter(pD, pd, sqrt(sfx[kk] * sfx[kk] + sfy[kk] * sfy[kk])) *
+                       grad_factor(a.grad, a.gx, a.gy, sfx[kk], sfy[kk]);
+            const double cb = amp * cv, sb = amp * sv;
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+                acc[q] = fma(sC[q][2 * kk], cb, fma(sC[q][2 * kk + 1], sb, acc[q]));
+        }
+    }
+    double* out = (double*)a.out;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int64_t r = row_begin + q;
+        if (r < row_end && pok) out[r * a.P + p] = acc[q];
+    }
+}
+
 // --------------------------------------------------------- MFMA kernel ----
 // One block = WV waves (WV = blockDim.x / 64 in 1..4).  Wave v owns rows
 // [32 MW v, 32 MW (v+1)) of the tile and all NT = 32 NB columns, so each
@@ -308,6 +408,92 @@ __device__ __forceinline__ void coef4_src(const SumArgs& a, int64_t row, bool ro
         // masking would split the Philox chains into separate basic blocks
         if constexpr (CSRC == 0) gauss4_f32(a.seed, a.counter + (uint64_t)row, t, g);
         else coef4_f32(a.seed, a.counter + (uint64_t)row, t, 1, g);
+    }
+}
+
+// ------------------------------------- FP32 class, narrow frequency sets ----
+// Sets of at most 8 realisations in the FP32-class precisions: a matrix-core
+// tile needs 32 rows, so these run on the vector ALU, one point per thread
+// and RB rows per block, with the arithmetic of the FP32 path (FP64 range
+// reduction, the same FP32 basis and coefficients as the MFMA kernels, FP32
+// sums folded into a second FP32 accumulator every 64 frequencies).  The
+// split-BF16 and BF16x6 precisions get these FP32 sums too (at least their
+// accuracy).
+template <int BASIS, int RB, int CSRC>
+__global__ __launch_bounds__(256) void k_sum_f32n(SumArgs a, int64_t col_tiles) {
+    constexpr int KCN = 64;
+    __shared__ double sfx[KCN], sfy[KCN], sw[KCN];
+    __shared__ float sC[RB][2 * KCN];
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    const int64_t ct = (int64_t)blockIdx.x % col_tiles;
+    const int64_t sl = (int64_t)blockIdx.x / col_tiles;
+    const int64_t set = a.set0 + sl;
+    const int64_t row_begin = set * a.R_block;
+    const int64_t set_end = (set + 1) * a.R_block < a.R ? (set + 1) * a.R_block : a.R;
+    const int64_t row_end = row_begin + RB < set_end ? row_begin + RB : set_end;
+    const int64_t p = ct * nt + tid;
+    const bool pok = p < a.P;
+    const double px = pok ? a.px[p] : 0.0;
+    const double py = pok ? a.py[p] : 0.0;
+    double pD = 1.0, pd = 0.0;
+    if (BASIS == BASIS_PISTON && pok) {
+        pD = a.apD[p];
+        pd = a.apd[p];
+    }
+    const double* fx = a.fx + sl * a.K;
+    const double* fy = a.fy + sl * a.K;
+    const double* w = a.w + sl * a.K;
+    float acc[RB], mst[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = mst[q] = 0.0f;
+
+    for (int64_t k0 = 0; k0 < a.K; k0 += KCN) {
+        __syncthreads();
+        if (tid < KCN) {
+            const int64_t k = k0 + tid;
+            const bool ok = k < a.K;
+            sfx[tid] = ok ? fx[k] : 0.0;
+            sfy[tid] = ok ? fy[k] : 0.0;
+            sw[tid] = ok ? w[k] : 0.0;
+        }
+        for (int i = tid; i < RB * (KCN / 2); i += nt) {
+            const int rr = i / (KCN / 2);
+            const int bt = i % (KCN / 2);
+            const int64_t r = row_begin + rr;
+            float g[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (r < row_end) coef4_src<CSRC>(a, r, true, (uint32_t)(k0 / 2 + bt), g);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sC[rr][4 * bt + q] = g[q];
+        }
+        __syncthreads();
+        const int nk = a.K - k0 < KCN ? (int)(a.K - k0) : KCN;
+        for (int kk = 0; kk < nk; ++kk) {
+            const double cfx = sfx[kk], cfy = sfy[kk];
+            double t = cfx * px + cfy * py;
+            double amp = sw[kk];
+            if (BASIS == BASIS_PISTON) {
+                amp *= aperture_filter(pD, pd, sqrt(cfx * cfx + cfy * cfy)) *
+                       grad_factor(a.grad, a.gx, a.gy, cfx, cfy);
+                t += grad_shift(a.grad);
+            }
+            float cb, sb;
+            basis_pair<BASIS>(t, amp, cb, sb);
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+                acc[q] = fmaf(sC[q][2 * kk], cb, fmaf(sC[q][2 * kk + 1], sb, acc[q]));
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            mst[q] += acc[q];
+            acc[q] = 0.0f;
+        }
+    }
+    float* out = (float*)a.out;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int64_t r = row_begin + q;
+        if (r < row_end && pok) out[r * a.P + p] = mst[q];
     }
 }
 
@@ -822,8 +1008,25 @@ SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P) 
     return p;
 }
 
+template <int BASIS, int RB>
+static hipError_t launch_f64n(const SumArgs& a, hipStream_t st) {
+    const int nt = a.P >= 256 ? 256 : (a.P >= 128 ? 128 : 64);
+    const int64_t col_tiles = cdiv(a.P, nt);
+    const int64_t blocks = (a.set1 - a.set0) * col_tiles;
+    hipLaunchKernelGGL((k_sum_f64n<BASIS, RB>), dim3((unsigned)blocks), dim3(nt), 0, st, a,
+                       col_tiles);
+    return hipGetLastError();
+}
+
 template <int BASIS, int EPI>
 static hipError_t launch_f64(const SumArgs& a, hipStream_t st) {
+    if constexpr (EPI == EPI_STORE) {
+        // sets of at most 8 realisations: one point per thread, no empty rows
+        if (a.R_block == 1) return launch_f64n<BASIS, 1>(a, st);
+        if (a.R_block == 2) return launch_f64n<BASIS, 2>(a, st);
+        if (a.R_block <= 4) return launch_f64n<BASIS, 4>(a, st);
+        if (a.R_block <= 8) return launch_f64n<BASIS, 8>(a, st);
+    }
     int64_t row_tiles = cdiv(a.R_block, F64_TR);
     int64_t col_tiles = cdiv(a.P, F64_TP);
     int64_t blocks = (a.set1 - a.set0) * row_tiles * col_tiles;
@@ -863,9 +1066,34 @@ static hipError_t launch_mfma(const SumArgs& a, hipStream_t st) {
     }
 }
 
+template <int BASIS, int RB>
+static hipError_t launch_f32n_r(const SumArgs& a, hipStream_t st) {
+    const int nt = a.P >= 256 ? 256 : (a.P >= 128 ? 128 : 64);
+    const int64_t col_tiles = cdiv(a.P, nt);
+    const dim3 g((unsigned)((a.set1 - a.set0) * col_tiles)), b(nt);
+    if (a.coef)
+        hipLaunchKernelGGL((k_sum_f32n<BASIS, RB, 2>), g, b, 0, st, a, col_tiles);
+    else if (a.mode == 1)
+        hipLaunchKernelGGL((k_sum_f32n<BASIS, RB, 1>), g, b, 0, st, a, col_tiles);
+    else
+        hipLaunchKernelGGL((k_sum_f32n<BASIS, RB, 0>), g, b, 0, st, a, col_tiles);
+    return hipGetLastError();
+}
+
+template <int BASIS>
+static hipError_t launch_f32n(const SumArgs& a, hipStream_t st) {
+    if (a.R_block == 1) return launch_f32n_r<BASIS, 1>(a, st);
+    if (a.R_block == 2) return launch_f32n_r<BASIS, 2>(a, st);
+    if (a.R_block <= 4) return launch_f32n_r<BASIS, 4>(a, st);
+    return launch_f32n_r<BASIS, 8>(a, st);
+}
+
 template <int BASIS, int EPI>
 static hipError_t launch_be(int precision, const SumArgs& a, hipStream_t st) {
     if (precision == 0) return launch_f64<BASIS, EPI>(a, st);
+    // FP32 class, sets of at most 8 realisations: vector ALU (see k_sum_f32n)
+    if constexpr (EPI == EPI_STORE)
+        if (a.R_block <= 8) return launch_f32n<BASIS>(a, st);
     if (precision == 1) return launch_mfma<1, BASIS, EPI>(a, st);
     if (precision == 2) return launch_mfma<2, BASIS, EPI>(a, st);
     return launch_mfma<3, BASIS, EPI>(a, st);
