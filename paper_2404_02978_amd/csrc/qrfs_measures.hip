@@ -40,7 +40,8 @@ __global__ __launch_bounds__(SS_THREADS) void k_set_sf(const double* __restrict_
 #pragma unroll
             for (int q = 0; q < SS_NB; ++q) {
                 const double r = frac_centered(f0 * cbx[q] + f1 * cby[q]);
-                const double sh = sinpi(r);
+                double sh, ch;
+                sincos2pi_reduced(0.5 * r, sh, ch);
                 acc[q] += w2 * 4.0 * sh * sh;
             }
         }
