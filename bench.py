@@ -40,6 +40,12 @@ OPS_PER_COEF = {"bf16x6": 27.5, "split_bf16": 25.0}
 # per (frequency, column, row tile): FP64 product and range reduction (5),
 # difference basis sin, sin^2 (5), amplitude (2), split of 2 values
 OPS_PER_BASIS = {"bf16x6": 23.0, "split_bf16": 18.0}
+# one realisation per set (k_sf_one): generator without the operand split;
+# per (frequency, baseline) the FP64 argument (2) and its reduction (2), a
+# conversion, the difference basis (2 sines, 3 products), the amplitude (2)
+# and the two FMAs of the contraction
+OPS_PER_COEF_F32 = 22.0
+OPS_PER_BASIS_ONE = 14.0
 PREC_IDS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "bf16x6": 3}
 # MFMA FLOPs executed per algorithmic flop (split-BF16 runs 3 products, BF16x6 six)
 MFMA_PASSES = {"fp32": 1, "split_bf16": 3, "bf16x6": 6, "fp64": 1}
@@ -563,7 +569,16 @@ def main():
                  "mfma_passes": MFMA_PASSES[args.precision]}
     kern = ("k_sum_mfma<diff, sfsum> + k_sfsum_rows + k_reduce_sf (event-timed per launch on "
             "the stream they run on)")
-    if args.precision in OPS_PER_COEF:
+    if Rb == 1 and nB <= 64 and args.precision != "fp64":
+        # one realisation per set: k_sf_one, FP32 on the vector ALU whatever
+        # the FP32-class precision (no operand split, no MFMA)
+        kern = "k_sf_one + k_reduce_sf (event-timed per launch on the stream they run on)"
+        ops = R * 2.0 * K * OPS_PER_COEF_F32 + R * K * nB * OPS_PER_BASIS_ONE
+        a_ops = ops / (avg_kernel_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": a_ops, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                "frac": a_ops / VALU_PEAK_TOPS, "traffic": None, "ops_per_launch": ops,
+                "kernel": kern, "kernel_ms": avg_kernel_ms}
+    elif args.precision in OPS_PER_COEF:
         # generator-bound: the coefficients are drawn by the vector ALU while
         # the bf16 MFMAs run beside it on the matrix cores
         row_tiles = math.ceil(Rb / 128)

@@ -91,6 +91,9 @@ struct SfPlan {
     int64_t n_partial_tiles;
 };
 SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P);
+// Sets of one realisation and at most 64 baselines: the structure function
+// runs in k_sf_one (one block per realisation, one partial tile per set).
+bool sf_one_realisation(int64_t R_block, int64_t P);
 
 // One work item of a persistent batch: instance, set, row tile, column tile.
 struct BatchItem {

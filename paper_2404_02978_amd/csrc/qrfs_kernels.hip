@@ -500,6 +500,97 @@ __global__ __launch_bounds__(256) void k_sum_f32n(SumArgs a, int64_t col_tiles) 
     }
 }
 
+// ----------------------- structure function, one realisation per set ----
+// Differential-piston structure function when every realisation has its
+// own frequencies (R_block = 1, as the paper draws them) and there are at
+// most NPM baselines.  One block per realisation: thread t draws Philox
+// blocks t, t + 256, ... (frequencies 2 t and 2 t + 1 of each) and keeps one
+// accumulator per baseline; the 256 partial differential pistons of a
+// baseline are added in a fixed tree (lanes by xor shuffles, then the 4
+// waves in order), and the block writes dp^2 and dp^4 as the set's partial
+// sums.  T = float: the FP32 path's coefficients and basis; T = double:
+// the FP64 path's.
+template <typename T, int NPM, int CSRC>
+__global__ __launch_bounds__(256) void k_sf_one(SumArgs a) {
+    __shared__ double2 sB[NPM];
+    __shared__ double red[4][NPM];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int64_t sl = blockIdx.x;
+    const int64_t row = (a.set0 + sl) * a.R_block;  // R_block == 1
+    const int nb = (int)a.P;
+    for (int b = tid; b < NPM; b += 256)
+        sB[b] = b < nb ? make_double2(a.px[b], a.py[b]) : make_double2(0.0, 0.0);
+    __syncthreads();
+    const double* fx = a.fx + sl * a.K;
+    const double* fy = a.fy + sl * a.K;
+    const double* w = a.w + sl * a.K;
+    T acc[NPM];
+#pragma unroll
+    for (int b = 0; b < NPM; ++b) acc[b] = (T)0;
+    const int64_t nblk = (a.K + 1) / 2;
+    for (int64_t t = tid; t < nblk; t += 256) {
+        T g[4];
+        if constexpr (sizeof(T) == 4) {
+            float gf[4];
+            coef4_src<CSRC>(a, row, true, (uint32_t)t, gf);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) g[q] = gf[q];
+        } else if constexpr (CSRC == 2) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t j = 4 * t + q;
+                g[q] = j < 2 * a.K ? a.coef[row * 2 * a.K + j] : 0.0;
+            }
+        } else {
+            double gd[4];
+            coef4_f64(a.seed, a.counter + (uint64_t)row, (uint32_t)t, CSRC, gd);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) g[q] = gd[q];
+        }
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            const int64_t k = 2 * t + h;
+            if (k >= a.K) break;
+            const double cfx = fx[k], cfy = fy[k], amp = w[k];
+#pragma unroll
+            for (int b = 0; b < NPM; ++b) {
+                if (b < nb) {
+                    const double2 B = sB[b];
+                    const double ta = cfx * B.x + cfy * B.y;
+                    if constexpr (sizeof(T) == 4) {
+                        float cb, sb;
+                        basis_pair<BASIS_DIFF>(ta, amp, cb, sb);
+                        acc[b] = fmaf(g[2 * h], cb, fmaf(g[2 * h + 1], sb, acc[b]));
+                    } else {
+                        double sh, ch;
+                        sincos2pi_reduced(0.5 * frac_centered(ta), sh, ch);
+                        const double cb = amp * (-2.0 * sh * sh), sb = amp * (2.0 * sh * ch);
+                        acc[b] = fma(g[2 * h], cb, fma(g[2 * h + 1], sb, acc[b]));
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NPM; ++b) {
+        if (b < nb) {
+            double v = (double)acc[b];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) red[wave][b] = v;
+        }
+    }
+    __syncthreads();
+    if (tid < nb) {
+        const double dp = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+        const double d2 = dp * dp;
+        double* dst = a.partial + (sl * a.P + tid) * 2;
+        dst[0] = d2;
+        dst[1] = d2 * d2;
+    }
+}
+
 // LDS of one block of the MFMA kernel
 template <int PREC, int NB>
 struct MfmaSmem {
@@ -987,6 +1078,8 @@ int64_t sum_col_tiles(int precision, int basis, int64_t R_block, int64_t P) {
     return cdiv(P, 32 * s.NB);
 }
 
+bool sf_one_realisation(int64_t R_block, int64_t P) { return R_block == 1 && P <= 64; }
+
 SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P) {
     SfPlan p;
     const int64_t n_sets = cdiv(R, R_block);
@@ -994,7 +1087,8 @@ SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P) 
     const int64_t cts = sum_col_tiles(precision, BASIS_DIFF, R_block, P);
     const int64_t base = n_sets * rts * cts;
     int64_t ks = 1;
-    if (precision != 0) {
+    // one realisation per set: k_sf_one spreads the frequencies over a block
+    if (precision != 0 && !sf_one_realisation(R_block, P)) {
         // aim for >= 6 waves of blocks per resident slot (256 CUs x 4 blocks)
         const int64_t target = 6 * 256 * 4;
         const int64_t nch = cdiv(K, KC);
@@ -1091,8 +1185,28 @@ static hipError_t launch_f32n(const SumArgs& a, hipStream_t st) {
     return launch_f32n_r<BASIS, 8>(a, st);
 }
 
+template <typename T, int NPM>
+static hipError_t launch_sf_one_t(const SumArgs& a, hipStream_t st) {
+    const dim3 g((unsigned)(a.set1 - a.set0)), b(256);
+    if (a.coef)
+        hipLaunchKernelGGL((k_sf_one<T, NPM, 2>), g, b, 0, st, a);
+    else if (a.mode == 1)
+        hipLaunchKernelGGL((k_sf_one<T, NPM, 1>), g, b, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_sf_one<T, NPM, 0>), g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+static hipError_t launch_sf_one(int precision, const SumArgs& a, hipStream_t st) {
+    if (precision == 0)
+        return a.P <= 32 ? launch_sf_one_t<double, 32>(a, st) : launch_sf_one_t<double, 64>(a, st);
+    return a.P <= 32 ? launch_sf_one_t<float, 32>(a, st) : launch_sf_one_t<float, 64>(a, st);
+}
+
 template <int BASIS, int EPI>
 static hipError_t launch_be(int precision, const SumArgs& a, hipStream_t st) {
+    if constexpr (EPI == EPI_SFSUM)
+        if (sf_one_realisation(a.R_block, a.P)) return launch_sf_one(precision, a, st);
     if (precision == 0) return launch_f64<BASIS, EPI>(a, st);
     // FP32 class, sets of at most 8 realisations: vector ALU (see k_sum_f32n)
     if constexpr (EPI == EPI_STORE)
