@@ -200,7 +200,9 @@ typedef struct {
  *               adds into the output every 2048); output float.
  *   (All FP32-class precisions sum sets of at most 8 realisations on the
  *   vector ALU with this FP32 arithmetic: a matrix-core tile needs 32 rows.
- *   The split-BF16 and BF16x6 results are then those FP32 sums.)
+ *   The split-BF16 and BF16x6 results are then those FP32 sums.  Their
+ *   per-aperture filter of Eq. 7 (qrfs_piston, qrfs_tilt) is evaluated in
+ *   binary32 like the basis it scales; FP64 evaluates it in binary64.)
  *   SPLIT_BF16  as FP32 but each operand is split into bf16 hi + lo and the
  *               contraction is hi.hi + hi.lo + lo.hi on bf16 MFMA with FP32
  *               accumulation (~16 significant bits); output float.

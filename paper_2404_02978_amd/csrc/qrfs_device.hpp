@@ -180,6 +180,18 @@ __device__ __forceinline__ double aperture_filter(double D, double d, double f) 
     return 2.0 * num / (pi * (D * D - d * d) * f);
 }
 
+// The same filter for the FP32-class paths, whose basis values are binary32:
+// the argument pi D f is formed in binary64 and rounded once, J1 is
+// evaluated in binary32 (absolute errors of a few 1e-8 where the filter is
+// large, tiny ones where it is small).
+__device__ __forceinline__ float aperture_filter_f32(double D, double d, double f) {
+    if (f == 0.0) return 1.0f;
+    const double pi = 3.141592653589793;
+    float num = (float)D * j1f((float)(pi * D * f));
+    if (d > 0.0) num -= (float)d * j1f((float)(pi * d * f));
+    return 2.0f * num / (float)(pi * (D * D - d * d) * f);
+}
+
 // Fractional part of t to [-1/2, 1/2] in binary64 (exact).
 __device__ __forceinline__ double frac_centered(double t) { return t - rint(t); }
 

@@ -476,7 +476,7 @@ __global__ __launch_bounds__(256) void k_sum_f32n(SumArgs a, int64_t col_tiles) 
             double t = cfx * px + cfy * py;
             double amp = sw[kk];
             if (BASIS == BASIS_PISTON) {
-                amp *= aperture_filter(pD, pd, sqrt(cfx * cfx + cfy * cfy)) *
+                amp *= (double)aperture_filter_f32(pD, pd, sqrt(cfx * cfx + cfy * cfy)) *
                        grad_factor(a.grad, a.gx, a.gy, cfx, cfy);
                 t += grad_shift(a.grad);
             }
@@ -705,7 +705,7 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
         const double sh = BASIS == BASIS_PISTON ? grad_shift(a.grad) : 0.0;
         for (int pp = pp0; pp < NT; pp += cstep) {
             double amp = gw;
-            if (BASIS == BASIS_PISTON) amp *= aperture_filter(sD[pp], sd[pp], fmag);
+            if (BASIS == BASIS_PISTON) amp *= (double)aperture_filter_f32(sD[pp], sd[pp], fmag);
             float cb, sb;
             basis_pair<BASIS>(cfx * spx[pp] + cfy * spy[pp] + sh, amp, cb, sb);
             if constexpr (PREC == 1) {

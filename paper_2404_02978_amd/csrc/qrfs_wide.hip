@@ -259,7 +259,7 @@ struct WideTile {
             double amp = bcast_lane(f2, kk);
             double t = cfx * px + cfy * py;
             if (BASIS == BASIS_PISTON) {
-                amp *= aperture_filter(pD, pd, sqrt(cfx * cfx + cfy * cfy)) *
+                amp *= (double)aperture_filter_f32(pD, pd, sqrt(cfx * cfx + cfy * cfy)) *
                        grad_factor(a.grad, a.gx, a.gy, cfx, cfy);
                 t += grad_shift(a.grad);
             }
