@@ -83,7 +83,9 @@ size_t wide_frag_bytes_per_row32(int precision, int64_t nkv) {
 }
 
 // ------------------------------------------------------ phase 1 ----
-// One thread per (set, 32-row tile, fragment column, lane).
+// One thread per (set, 32-row tile, fragment column, lane).  The tiles hold
+// w_k c_rk: the frequency's amplitude is applied once per coefficient here
+// rather than once per (frequency, point, row tile) in the basis.
 template <int PREC, int CSRC>
 __global__ __launch_bounds__(256) void k_coef_tiles(WideArgs wa, int64_t n_threads) {
     using C = WideCfg<PREC>;
@@ -105,6 +107,7 @@ __global__ __launch_bounds__(256) void k_coef_tiles(WideArgs wa, int64_t n_threa
     const uint64_t real = (uint64_t)(set * a.R_block + row);
     const int h = lane >> 5;
     const int64_t twoK = 2 * a.K;
+    const double* wk = a.w + sl * a.K;
     constexpr int NV = C::KB / 2;  // values per lane: 4 (FP32) or 8 (BF16)
     const int64_t j0 = kb * C::KB + (int64_t)h * NV;
     float v[NV];
@@ -128,7 +131,10 @@ __global__ __launch_bounds__(256) void k_coef_tiles(WideArgs wa, int64_t n_threa
             }
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[q + e] = g4[e];
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = j0 + q + e;
+            v[q + e] = j < twoK ? (float)((double)g4[e] * wk[j >> 1]) : 0.0f;
+        }
     }
     const int64_t frag = (sl * wa.rt32 + rt) * NKB + kb;
     if constexpr (PREC == 1) {
@@ -256,11 +262,13 @@ struct WideTile {
             const int kk = g * GF + i;  // wave-uniform
             const double cfx = bcast_lane(f0, kk);
             const double cfy = bcast_lane(f1, kk);
-            double amp = bcast_lane(f2, kk);
             double t = cfx * px + cfy * py;
+            // the amplitude w_k sits in the coefficient tiles; pistons add
+            // their aperture's filter (and the gradient factor) here
+            double amp = 1.0;
             if (BASIS == BASIS_PISTON) {
-                amp *= (double)aperture_filter_f32(pD, pd, sqrt(cfx * cfx + cfy * cfy)) *
-                       grad_factor(a.grad, a.gx, a.gy, cfx, cfy);
+                amp = (double)aperture_filter_f32(pD, pd, sqrt(cfx * cfx + cfy * cfy)) *
+                      grad_factor(a.grad, a.gx, a.gy, cfx, cfy);
                 t += grad_shift(a.grad);
             }
             basis_pair<BASIS>(t, amp, v[2 * i], v[2 * i + 1]);
