@@ -876,9 +876,20 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
     }
 }
 
+// The one-tile structure-function kernels (MW = NB = 1, EPI_SFSUM) are bound by
+// vector issue: asking for five waves per SIMD instead of the four their
+// registers give (a handful of spills outside the frequency loop, 30 KB of
+// LDS per block) hides more of the transcendental and MFMA latency.  Caller-
+// given coefficients keep the default: at five waves they spill in the loop.
+template <int EPI, int MW, int NB, int CSRC>
+constexpr int sum_mfma_min_waves() {
+    return (EPI == EPI_SFSUM && MW * NB == 1 && CSRC != 2) ? 5 : 1;
+}
+
 template <int PREC, int BASIS, int EPI, int MW, int NB, int CSRC>
-__global__ __launch_bounds__(256) void k_sum_mfma(SumArgs a, int64_t row_tiles,
-                                                  int64_t col_tiles) {
+__global__ __launch_bounds__(256) __attribute__((
+    amdgpu_waves_per_eu(sum_mfma_min_waves<EPI, MW, NB, CSRC>(), 8))) void
+k_sum_mfma(SumArgs a, int64_t row_tiles, int64_t col_tiles) {
     __shared__ MfmaSmem<PREC, NB> sm;
     // tile: column tile fastest, then K split, row tile, set
     int64_t bidx = blockIdx.x;
