@@ -20,7 +20,9 @@
 //      operand split) into the other of two LDS buffers, interleaved with
 //      the MFMAs of the current chunk.  Coefficient fragments are loaded one
 //      contraction step ahead, the frequencies two chunks ahead (lanes
-//      0..KCH-1 hold one frequency each; lanes read them by readlane).
+//      0..KCH-1 hold one frequency each).  BF16 precisions stage each
+//      chunk's frequencies in LDS and read them by broadcast; FP32 reads
+//      them from the holding lanes (readlane).
 // Blocks are remapped so that the blocks one XCD runs together share a row
 // panel and walk the column tiles: each XCD streams a coefficient panel
 // through its own L2 once per round of blocks.
@@ -161,6 +163,9 @@ struct WideSmem {
     static constexpr int NPL = WideCfg<PREC>::NPL;
     static constexpr int STR = WideCfg<PREC>::STR;
     __attribute__((aligned(16))) T b[2][NPL][WT * STR];
+    // BF16 precisions: (fx, fy) of the chunk whose basis is being built,
+    // slot = lane, zeros past the chunk
+    double2 fq[PREC >= 2 ? 2 : 1][64];
 };
 
 __device__ __forceinline__ double bcast_lane(double v, int l) {
@@ -244,6 +249,12 @@ struct WideTile {
         if (!ok) f0 = f1 = f2 = 0.0;
     }
 
+    // BF16: every wave writes its copy of a chunk's frequencies (identical
+    // values; lanes past the chunk hold zeros) into frequency buffer fb
+    __device__ __forceinline__ void stage(int fb, const double (&f)[3]) {
+        if constexpr (PREC >= 2) sm.fq[fb][lane] = make_double2(f[0], f[1]);
+    }
+
     // fragments of contraction step kb (all row blocks and planes)
     __device__ __forceinline__ void load_step(int64_t kb, Frag (&fa)[MB][NPL]) const {
 #pragma unroll
@@ -260,8 +271,18 @@ struct WideTile {
 #pragma unroll
         for (int i = 0; i < GF; ++i) {
             const int kk = g * GF + i;  // wave-uniform
-            const double cfx = bcast_lane(f0, kk);
-            const double cfy = bcast_lane(f1, kk);
+            // BF16: one LDS read at a wave-uniform address (a broadcast)
+            // instead of four lane reads on the vector ALU; FP32, whose
+            // MFMAs leave the ALU idle longer, keeps the lane reads
+            double cfx, cfy;
+            if constexpr (PREC >= 2) {
+                const double2 fk = sm.fq[buf][kk];
+                cfx = fk.x;
+                cfy = fk.y;
+            } else {
+                cfx = bcast_lane(f0, kk);
+                cfy = bcast_lane(f1, kk);
+            }
             double t = cfx * px + cfy * py;
             // the amplitude w_k sits in the coefficient tiles; pistons add
             // their aperture's filter (and the gradient factor) here
@@ -357,6 +378,9 @@ struct WideTile {
                     produce((s / (2 * NPART)) * NPART + part, buf ^ 1, fcur[0], fcur[1], fcur[2]);
             }
         }
+        // chunk ch + 2 goes into the frequency buffer chunk ch's basis was
+        // built from; its last readers passed the barrier ending chunk ch - 1
+        stage(buf, fnxt);
     }
 
     // stores the accumulators into the output (first range of the tile) or
@@ -427,6 +451,11 @@ __device__ __forceinline__ void wide_tile_run(WideSmem<PREC>& sm, const WideArgs
     T.load_freq(0, fq2[0], fq2[1], fq2[2]);
     T.load_step(T.c0 * NSTEP, F[0]);
     T.load_freq(1, fq0[0], fq0[1], fq0[2]);
+    if constexpr (PREC >= 2) {
+        T.stage(0, fq2);
+        T.stage(1, fq0);
+        __syncthreads();
+    }
 #pragma unroll
     for (int g = 0; g < Tile::NGRP; ++g) T.produce(g * NPART + T.part, 0, fq2[0], fq2[1], fq2[2]);
     __syncthreads();
