@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqrfs.so")
-SOURCES = ["qrfs_kernels.hip", "qrfs_wide.hip", "qrfs_temporal.hip", "qrfs_measures.hip",
+SOURCES = ["qrfs_frequencies.hip", "qrfs_kernels.hip", "qrfs_wide.hip", "qrfs_temporal.hip", "qrfs_measures.hip",
            "qrfs_pairs.hip", "qrfs_proposal.hip", "qrfs_api.cpp", "qrfs_batch.cpp", "qrfs_proposal_api.cpp",
            "qrfs_plan.cpp"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-Werror",

@@ -1,86 +1,14 @@
 // qrfs_kernels.hip -- gfx950 kernels of the quasi-random frequency sampling
-// path (arXiv 2404.02978): R2 sampler, PSD/aperture weights, the fused
-// coefficient x basis contraction of Eq. 3 (FP64 vector ALU, FP32 MFMA and
-// split-BF16 MFMA), and the fixed-order structure-function reduction.
+// path (arXiv 2404.02978): the fused coefficient x basis contraction of
+// Eq. 3 (FP64 vector ALU, FP32 MFMA, split-BF16 and BF16x6 MFMA), its
+// epilogues and the fixed-order structure-function reduction.  The sampler
+// and the weights live in qrfs_frequencies.hip.
 #include "qrfs_device.hpp"
 #include "qrfs_internal.hpp"
 #include "qrfs_mfma.hpp"
 
 namespace qrfs {
 
-
-// ------------------------------------------------------------- sampler ----
-// One thread per frequency.  Point n = index + 1 + i of the R2 sequence
-// (Sec. 3.2, Eq. 6) for schemes 0, 1, 3, of the pseudo-random stream for
-// schemes 4-7 (the randomised samplers of Sec. 3.1), mapped by Eq. 5
-// (Cartesian: schemes 0, 5), the log-polar map (1, 6), the square-to-disc
-// map (3, 7), or placed in its cell of the jittered grid of Eq. 4 (4).
-__global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n,
-                         int64_t K, int32_t N, double df, double L, double fmin, double lr,
-                         double* __restrict__ fx, double* __restrict__ fy,
-                         double* __restrict__ area) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double ux, uy;
-    if (scheme >= 4)
-        pseudo_point(s0x, s0y, index + 1u + (uint64_t)i, ux, uy);
-    else
-        r2_point(s0x, s0y, index + 1u + (uint64_t)i, ux, uy);
-    const int map = scheme >= 5 ? (scheme == 7 ? 3 : scheme - 5) : scheme;
-    if (map == 0) {
-        fx[i] = L * (ux - 0.5);
-        fy[i] = L * (uy - 0.5);
-        area[i] = L * L / (double)K;
-    } else if (map == 4) {
-        // Eq. 4: point k = iy N + ix of a set (K = N^2) at its cell's lower
-        // corner -N df / 2 + i df plus the jitter u df, as df (i + u - N/2)
-        // (no product feeds a sum, so nothing is fused)
-        const int64_t k = i % K;
-        const double ix = (double)(k % N), iy = (double)(k / N);
-        const double h = 0.5 * (double)N;
-        fx[i] = df * (ix + ux - h);
-        fy[i] = df * (iy + uy - h);
-        area[i] = df * df;
-    } else if (map == 3) {
-        // polar quasi-random frequencies (Sec. 3.2): concentric square-to-
-        // disc map of the point, disc radius L, equal cell areas
-        const double a = 2.0 * ux - 1.0, b = 2.0 * uy - 1.0;
-        double rad = 0.0, ang = 0.0;  // angle in half-turns
-        if (fabs(a) > fabs(b)) {
-            rad = a;
-            ang = 0.25 * (b / a);
-        } else if (b != 0.0) {
-            rad = b;
-            ang = 0.5 - 0.25 * (a / b);
-        }
-        double s, c;
-        sincospi(ang, &s, &c);
-        fx[i] = L * rad * c;
-        fy[i] = L * rad * s;
-        area[i] = 3.141592653589793 * L * L / (double)K;
-    } else {
-        double f = fmin * exp(lr * ux);
-        double s, c;
-        sincospi(2.0 * uy, &s, &c);
-        fx[i] = f * c;
-        fy[i] = f * s;
-        area[i] = 2.0 * 3.141592653589793 * lr * f * f / (double)K;
-    }
-}
-
-// ------------------------------------------------------------- weights ----
-// w = sqrt(W(|f|) area) [x F(|f|)], the amplitude of Eq. 3 (Eq. 7 filter).
-__global__ void k_weights(int model, double c, double r0_m53, double inv_L02, int has_ap,
-                          double D, double d, int64_t n, const double* __restrict__ fx,
-                          const double* __restrict__ fy, const double* __restrict__ area,
-                          double* __restrict__ w) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double f = sqrt(fx[i] * fx[i] + fy[i] * fy[i]);
-    double v = sqrt(psd_phase(model, c, r0_m53, inv_L02, f) * area[i]);
-    if (has_ap) v *= aperture_filter(D, d, f);
-    w[i] = v;
-}
 
 // --------------------------------------------------- tile bookkeeping ----
 struct TileInfo {
@@ -1028,27 +956,6 @@ __global__ __launch_bounds__(256) void k_reduce_sf(const double* __restrict__ pa
 
 // ----------------------------------------------------------- launchers ----
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-hipError_t launch_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n_sets,
-                         int64_t K, int32_t N, double df, double fmin, double fmax, double* fx,
-                         double* fy, double* area, hipStream_t st) {
-    int64_t n = n_sets * K;
-    double L = (scheme == 3 || scheme == 7) ? fmax : (double)N * df;
-    double lr = (scheme == 1 || scheme == 6) ? log(fmax / fmin) : 0.0;
-    hipLaunchKernelGGL(k_sample, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, scheme, s0x, s0y,
-                       index, n, K, N, df, L, fmin, lr, fx, fy, area);
-    return hipGetLastError();
-}
-
-hipError_t launch_weights(int model, double c, double r0, double L0, int has_ap, double D,
-                          double d, int64_t n, const double* fx, const double* fy,
-                          const double* area, double* w, hipStream_t st) {
-    double r0_m53 = pow(r0, -5.0 / 3.0);
-    double inv_L02 = model == 1 ? 1.0 / (L0 * L0) : 0.0;
-    hipLaunchKernelGGL(k_weights, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, model, c, r0_m53,
-                       inv_L02, has_ap, D, d, n, fx, fy, area, w);
-    return hipGetLastError();
-}
 
 hipError_t launch_reduce_sf(const double* partial, int64_t n_tiles, int64_t P, int64_t R,
                             double* sf, double* sf_stderr, hipStream_t st) {
