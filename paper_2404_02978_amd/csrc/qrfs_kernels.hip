@@ -641,15 +641,11 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
                 dst[0] = cb;
                 dst[1] = sb;
             } else {
-                const int o = buf * NT * STR_H + pp * STR_H + 2 * kk;
-                __bf16 pc[NPL], ps[NPL];
-                split_bf16<NPL>(cb, pc);
-                split_bf16<NPL>(sb, ps);
+                const int o = buf * NT * STR_H + pp * STR_H + 2 * kk;  // even
+                uint32_t pcs[NPL];
+                split_bf16x2<NPL>(cb, sb, pcs);
 #pragma unroll
-                for (int i = 0; i < NPL; ++i) {
-                    sBp[i][o] = pc[i];
-                    sBp[i][o + 1] = ps[i];
-                }
+                for (int i = 0; i < NPL; ++i) *(uint32_t*)&sBp[i][o] = pcs[i];
             }
         }
 
@@ -690,13 +686,7 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
                     float g[8];
                     coef4_src<CSRC>(a, myrow[mw], rowok[mw], t, g);
                     coef4_src<CSRC>(a, myrow[mw], rowok[mw], t + 1u, g + 4);
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        __bf16 part[NPL];
-                        split_bf16<NPL>(g[q], part);
-#pragma unroll
-                        for (int i = 0; i < NPL; ++i) ap[sg][mw][i][q] = part[i];
-                    }
+                    split8_bf16<NPL>(g, ap[sg][mw]);
                 }
             }
             __syncthreads();
@@ -808,15 +798,16 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
 // vector issue: asking for five waves per SIMD instead of the four their
 // registers give (a handful of spills outside the frequency loop, 30 KB of
 // LDS per block) hides more of the transcendental and MFMA latency.  Caller-
-// given coefficients keep the default: at five waves they spill in the loop.
-template <int EPI, int MW, int NB, int CSRC>
+// given coefficients, and BF16x6 with Eq. 3 coefficients, keep the default:
+// at five waves they reload spilled registers inside the frequency loop.
+template <int PREC, int EPI, int MW, int NB, int CSRC>
 constexpr int sum_mfma_min_waves() {
-    return (EPI == EPI_SFSUM && MW * NB == 1 && CSRC != 2) ? 5 : 1;
+    return (EPI == EPI_SFSUM && MW * NB == 1 && (CSRC == 0 || (CSRC == 1 && PREC < 3))) ? 5 : 1;
 }
 
 template <int PREC, int BASIS, int EPI, int MW, int NB, int CSRC>
 __global__ __launch_bounds__(256) __attribute__((
-    amdgpu_waves_per_eu(sum_mfma_min_waves<EPI, MW, NB, CSRC>(), 8))) void
+    amdgpu_waves_per_eu(sum_mfma_min_waves<PREC, EPI, MW, NB, CSRC>(), 8))) void
 k_sum_mfma(SumArgs a, int64_t row_tiles, int64_t col_tiles) {
     __shared__ MfmaSmem<PREC, NB> sm;
     // tile: column tile fastest, then K split, row tile, set

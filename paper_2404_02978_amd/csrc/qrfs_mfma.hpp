@@ -15,16 +15,43 @@ __device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-// x = hi + mid (+ lo) in bf16, each part the rounding of the remainder
+// x = hi + mid (+ lo) in bf16, each part the rounding (to nearest even) of
+// the remainder left by the parts before it; split for two values at once:
+// plane i of (x0, x1) as one packed word, x0 in the low half (the element
+// order of the MFMA operands).  One pair conversion per plane; the
+// remainders take each half back to binary32 by a shift or a mask.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 template <int NPL>
-__device__ __forceinline__ void split_bf16(float x, __bf16 part[NPL]) {
-    float r = x;
+__device__ __forceinline__ void split_bf16x2(float x0, float x1, uint32_t part[NPL]) {
+    float r0 = x0, r1 = x1;
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
-        __bf16 h = (__bf16)r;
-        part[i] = h;
-        r -= (float)h;
+        const f32x2 r = {r0, r1};
+        const bf16x2 h = __builtin_convertvector(r, bf16x2);
+        const uint32_t u = __builtin_bit_cast(uint32_t, h);
+        part[i] = u;
+        if (i + 1 < NPL) {
+            r0 -= __uint_as_float(u << 16);
+            r1 -= __uint_as_float(u & 0xffff0000u);
+        }
     }
+}
+
+// Eight values (one MFMA operand register group) into NPL operand planes:
+// word j of each plane holds elements 2j and 2j + 1.
+template <int NPL>
+__device__ __forceinline__ void split8_bf16(const float (&v)[8], bf16x8 (&o)[NPL]) {
+    uint32_t w[NPL][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t part[NPL];
+        split_bf16x2<NPL>(v[2 * j], v[2 * j + 1], part);
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) w[i][j] = part[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) o[i] = __builtin_bit_cast(bf16x8, w[i]);
 }
 
 template <int BASIS>

@@ -144,13 +144,7 @@ __global__ __launch_bounds__(256) void k_coef_tiles(WideArgs wa, int64_t n_threa
         ((f32x4*)wa.ctile)[frag * 64 + lane] = o;
     } else {
         bf16x8 o[C::NPL];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            __bf16 part[C::NPL];
-            split_bf16<C::NPL>(v[e], part);
-#pragma unroll
-            for (int p = 0; p < C::NPL; ++p) o[p][e] = part[p];
-        }
+        split8_bf16<C::NPL>(v, o);
 #pragma unroll
         for (int p = 0; p < C::NPL; ++p) ((bf16x8*)wa.ctile)[(frag * C::NPL + p) * 64 + lane] = o[p];
     }
@@ -300,13 +294,7 @@ struct WideTile {
             *(f32x4*)&sm.b[buf][0][col * STR + 4 * g] = o;
         } else {
             bf16x8 o[NPL];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                __bf16 part[NPL];
-                split_bf16<NPL>(v[e], part);
-#pragma unroll
-                for (int p = 0; p < NPL; ++p) o[p][e] = part[p];
-            }
+            split8_bf16<NPL>(v, o);
 #pragma unroll
             for (int p = 0; p < NPL; ++p) *(bf16x8*)&sm.b[buf][p][col * STR + 8 * g] = o[p];
         }
