@@ -196,7 +196,7 @@ typedef struct {
  *   FP32        FP64 range reduction of 2 pi f.x, FP32 sincos and
  *               Box-Muller, FP32 matrix-core (MFMA) contraction with FP32
  *               accumulation, folded into a second FP32 accumulator every
- *               64 frequencies (the two-phase kernel for wide point sets
+ *               32 frequencies (the two-phase kernel for wide point sets
  *               adds into the output every 2048); output float.
  *   (All FP32-class precisions sum sets of at most 8 realisations on the
  *   vector ALU with this FP32 arithmetic: a matrix-core tile needs 32 rows.

@@ -76,8 +76,12 @@ __device__ __forceinline__ void pseudo_point(uint64_t seed_x, uint64_t seed_y, u
 }
 
 // 32-bit word -> (2m+1) 2^-24 with m = x >> 9: exact in binary32, in (0,1).
+// One funnel shift places m under the exponent of 1.0 (the bit pattern of
+// 1 + m 2^-23), and subtracting 1 - 2^-24 is exact (the difference has at
+// most 24 significant bits).
 __device__ __forceinline__ float word_uniform_f32(uint32_t x) {
-    return (float)(x >> 9) * 0x1p-23f + 0x1p-24f;
+    const uint32_t one_m = __builtin_amdgcn_alignbit(0x7fu, x, 9u);  // (x >> 9) | 0x3f800000
+    return __uint_as_float(one_m) - 0x1.fffffep-1f;
 }
 __device__ __forceinline__ double word_uniform_f64(uint32_t x) {
     return ((double)(x >> 9) + 0.5) * 0x1p-23;

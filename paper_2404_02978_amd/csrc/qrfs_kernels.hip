@@ -312,11 +312,12 @@ __global__ __launch_bounds__(256) void k_sum_f64n(SumArgs a, int64_t col_tiles) 
 //     coefficients j = 16 s + 8 h + 0..7, the natural order.
 // FP32 MFMA runs on the vector datapath and never overlaps the VALU work of
 // the generator; the BF16 MFMAs run on the matrix cores and do.
-// The MFMA accumulators are added to a second FP32 accumulator every FLUSH
-// chunks, which keeps the rounding error of long sums at
-// ~u (sqrt(64) + sqrt(K/64)) instead of ~u sqrt(K).
+// The MFMA accumulators are added to a second FP32 accumulator after every
+// chunk, which keeps the rounding error of long sums at
+// ~u (sqrt(32) + sqrt(K/32)) instead of ~u sqrt(K).  (A fold every second
+// chunk compiles to selects on every chunk, which cost more than the adds.)
 constexpr int KC = 32;
-constexpr int FLUSH = 2;
+constexpr int FLUSH = 1;
 constexpr int STR_F32 = 2 * KC + 4;  // floats per basis column (16-byte rows, skewed banks)
 constexpr int STR_H = 2 * KC + 8;    // 16-bit values per basis column
 
