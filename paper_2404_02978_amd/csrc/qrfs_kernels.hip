@@ -798,12 +798,12 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
 // The one-tile structure-function kernels (MW = NB = 1, EPI_SFSUM) are bound by
 // vector issue: asking for five waves per SIMD instead of the four their
 // registers give (a handful of spills outside the frequency loop, 30 KB of
-// LDS per block) hides more of the transcendental and MFMA latency.  Caller-
-// given coefficients, and BF16x6 with Eq. 3 coefficients, keep the default:
-// at five waves they reload spilled registers inside the frequency loop.
+// LDS per block) hides more of the transcendental and MFMA latency.  BF16x6
+// with Eq. 3 or caller-given coefficients keeps the default: at five waves
+// it reloads spilled registers inside the frequency loop.
 template <int PREC, int EPI, int MW, int NB, int CSRC>
 constexpr int sum_mfma_min_waves() {
-    return (EPI == EPI_SFSUM && MW * NB == 1 && (CSRC == 0 || (CSRC == 1 && PREC < 3))) ? 5 : 1;
+    return (EPI == EPI_SFSUM && MW * NB == 1 && (PREC < 3 || CSRC == 0)) ? 5 : 1;
 }
 
 template <int PREC, int BASIS, int EPI, int MW, int NB, int CSRC>
