@@ -482,21 +482,31 @@ __global__ __launch_bounds__(256) void k_sf_one(SumArgs a) {
             const int64_t k = 2 * t + h;
             if (k >= a.K) break;
             const double cfx = fx[k], cfy = fy[k], amp = w[k];
+            // one realisation: the amplitude and the constant factors of the
+            // difference basis, (cos 2 pi r - 1, sin 2 pi r) =
+            // (-2 sin^2 pi r, 2 sin pi r cos pi r), go into this frequency's two
+            // coefficients once instead of into every baseline's basis
             // baselines past nb are staged as (0, 0): their difference basis
             // is exactly 0 and their accumulators stay 0, so no branch
+            if constexpr (sizeof(T) == 4) {
+                const float fa = (float)amp;
+                const float ga = -2.0f * (g[2 * h] * fa), gb = g[2 * h + 1] * fa;
 #pragma unroll
-            for (int b = 0; b < NPM; ++b) {
-                const double2 B = sB[b];
-                const double ta = cfx * B.x + cfy * B.y;
-                if constexpr (sizeof(T) == 4) {
-                    float cb, sb;
-                    basis_pair<BASIS_DIFF>(ta, amp, cb, sb);
-                    acc[b] = fmaf(g[2 * h], cb, fmaf(g[2 * h + 1], sb, acc[b]));
-                } else {
+                for (int b = 0; b < NPM; ++b) {
+                    const double2 B = sB[b];
+                    const float r = (float)frac_centered(cfx * B.x + cfy * B.y);
+                    const float sh = __builtin_amdgcn_sinf(0.5f * r);  // sin(pi r)
+                    const float s2 = __builtin_amdgcn_sinf(r);         // sin(2 pi r)
+                    acc[b] = fmaf(ga, sh * sh, fmaf(gb, s2, acc[b]));
+                }
+            } else {
+                const double ga = -2.0 * (g[2 * h] * amp), gb = 2.0 * (g[2 * h + 1] * amp);
+#pragma unroll
+                for (int b = 0; b < NPM; ++b) {
+                    const double2 B = sB[b];
                     double sh, ch;
-                    sincos2pi_reduced(0.5 * frac_centered(ta), sh, ch);
-                    const double cb = amp * (-2.0 * sh * sh), sb = amp * (2.0 * sh * ch);
-                    acc[b] = fma(g[2 * h], cb, fma(g[2 * h + 1], sb, acc[b]));
+                    sincos2pi_reduced(0.5 * frac_centered(cfx * B.x + cfy * B.y), sh, ch);
+                    acc[b] = fma(ga, sh * sh, fma(gb, sh * ch, acc[b]));
                 }
             }
         }
