@@ -487,13 +487,19 @@ __global__ __launch_bounds__(256) void k_sf_one(SumArgs a) {
             // (-2 sin^2 pi r, 2 sin pi r cos pi r), go into this frequency's two
             // coefficients once instead of into every baseline's basis
             // baselines past nb are staged as (0, 0): their difference basis
-            // is exactly 0 and their accumulators stay 0, so no branch
+            // is exactly 0 and their accumulators stay 0, so no branch.
+            // The baselines are read from LDS (a broadcast) for every
+            // frequency: an offset the compiler cannot see through (a scalar
+            // register set to 0) keeps it from hoisting all NPM of them into
+            // registers, which would leave room for only 1-2 waves per SIMD.
+            int z;
+            asm volatile("s_mov_b32 %0, 0" : "=s"(z));
             if constexpr (sizeof(T) == 4) {
                 const float fa = (float)amp;
                 const float ga = -2.0f * (g[2 * h] * fa), gb = g[2 * h + 1] * fa;
 #pragma unroll
                 for (int b = 0; b < NPM; ++b) {
-                    const double2 B = sB[b];
+                    const double2 B = sB[b + z];
                     const float r = (float)frac_centered(cfx * B.x + cfy * B.y);
                     const float sh = __builtin_amdgcn_sinf(0.5f * r);  // sin(pi r)
                     const float s2 = __builtin_amdgcn_sinf(r);         // sin(2 pi r)
@@ -503,7 +509,7 @@ __global__ __launch_bounds__(256) void k_sf_one(SumArgs a) {
                 const double ga = -2.0 * (g[2 * h] * amp), gb = 2.0 * (g[2 * h + 1] * amp);
 #pragma unroll
                 for (int b = 0; b < NPM; ++b) {
-                    const double2 B = sB[b];
+                    const double2 B = sB[b + z];
                     double sh, ch;
                     sincos2pi_reduced(0.5 * frac_centered(cfx * B.x + cfy * B.y), sh, ch);
                     acc[b] = fma(ga, sh * sh, fma(gb, sh * ch, acc[b]));
