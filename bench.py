@@ -34,10 +34,10 @@ PEAKS = {"fp32": 157.3, "split_bf16": 2500.0, "bf16x6": 2500.0, "fp64": 78.6}  #
 # vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane op per cycle
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # algorithmic vector ops of the generator per coefficient: Philox4x32-10
-# (10 rounds x (2 products + 4 xor) per 4 words = 15), uniform (2: one funnel
-# shift and one subtraction), Box-Muller (4 per coefficient), operand split
-# (5.5 three-way, 3 two-way, two values per conversion)
-OPS_PER_COEF = {"bf16x6": 26.5, "split_bf16": 24.0}
+# (10 rounds x (2 products + 2 three-input xors) per 4 words = 10), uniform
+# (2: one funnel shift and one subtraction), Box-Muller (4 per coefficient),
+# operand split (5.5 three-way, 3 two-way, two values per conversion)
+OPS_PER_COEF = {"bf16x6": 21.5, "split_bf16": 19.0}
 # per (frequency, column, row tile): FP64 product and range reduction (5),
 # difference basis sin, sin^2 (5), amplitude (2), split of 2 values
 OPS_PER_BASIS = {"bf16x6": 23.0, "split_bf16": 18.0}
@@ -46,7 +46,7 @@ OPS_PER_BASIS = {"bf16x6": 23.0, "split_bf16": 18.0}
 # coefficients (2 per coefficient); per (frequency, baseline) the FP64
 # argument (2) and its reduction (2), a conversion, the difference basis
 # (2 sines, the half angle and a square) and the two FMAs of the contraction
-OPS_PER_COEF_F32 = 23.0
+OPS_PER_COEF_F32 = 18.0
 OPS_PER_BASIS_ONE = 11.0
 PREC_IDS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "bf16x6": 3}
 # MFMA FLOPs executed per algorithmic flop (split-BF16 runs 3 products, BF16x6 six)
@@ -56,8 +56,8 @@ DTYPES = {"fp32": "f32", "split_bf16": "bf16x3", "bf16x6": "bf16x6", "fp64": "f6
 # a 1 GiB copy (x2.0 / x1.0), valid only for the kernel source they were taken with
 # sources the structure-function kernels are built from (hashed together)
 KERNEL_SOURCES = ("qrfs_kernels.hip", "qrfs_mfma.hpp", "qrfs_device.hpp", "qrfs_internal.hpp")
-TRAFFIC = {"sha256_prefix": "2abb96bab4f2c5b2", "K": 16384, "R": 100000, "R_block": 256,
-           "bytes": {"bf16x6": 2.689e8, "fp32": 2.563e8}}
+TRAFFIC = {"sha256_prefix": "380a4421c205c5f6", "K": 16384, "R": 100000, "R_block": 256,
+           "bytes": {"bf16x6": 3.138e8, "fp32": 2.563e8}}
 
 
 def parse():

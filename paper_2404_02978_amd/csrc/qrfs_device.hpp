@@ -31,10 +31,16 @@ __device__ __forceinline__ void r2_point(uint64_t s0x, uint64_t s0y, uint64_t n,
 
 // --------------------------------------------------------------- Philox ----
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The 32x32->64 products
-// map onto v_mad_u64_u32; the key schedule is wave-uniform and stays scalar.
+// map onto v_mad_u64_u32; the key schedule is wave-uniform and stays scalar;
+// each round's two three-way xors are one v_bitop3_b32 each (truth table
+// 0x96 is the parity of the three inputs), not two v_xor_b32.
 struct U32x4 {
     uint32_t x, y, z, w;
 };
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
 
 __device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                uint32_t c3, uint32_t k0, uint32_t k1) {
@@ -42,8 +48,8 @@ __device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     for (int i = 0; i < 10; ++i) {
         uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
