@@ -63,7 +63,7 @@ typedef int32_t qrfs_status;
 #define QRFS_ERR_DEVICE (-3)        /* HIP runtime error (launch, fault)      */
 #define QRFS_ERR_UNSUPPORTED (-4)   /* valid but not implemented combination  */
 
-#define QRFS_ABI_VERSION 2
+#define QRFS_ABI_VERSION 3
 
 /* Static string for a status code. */
 QRFS_API const char* qrfs_error_string(qrfs_status s);
@@ -239,6 +239,18 @@ QRFS_API qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s,
 QRFS_API qrfs_status qrfs_weights(qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aperture* ap,
                          int64_t n, const double* fx, const double* fy, const double* area,
                          double* w, void* stream);
+
+/* qrfs_sample_frequencies followed by qrfs_weights in one pass, for callers
+ * that need the frequencies and their weights but not the cell areas
+ * (Sec. 3.2, Eqs. 5-7): writes fx, fy (cycles/m) and w, all
+ * double[n_sets*K], set-major, with the same values the two calls give.
+ * ap == NULL: phase weights; else the filter of equal apertures is folded
+ * in.  The learned sampler keeps its cell areas in the context's workspace
+ * (grown to n_sets*K doubles if needed).  s->index += n_sets*K on success.
+ * Errors: as qrfs_sample_frequencies and qrfs_weights. */
+QRFS_API qrfs_status qrfs_sample_weights(qrfs_context* ctx, qrfs_sampler* s, int64_t n_sets,
+                                         int64_t K, const qrfs_psd* psd, const qrfs_aperture* ap,
+                                         double* fx, double* fy, double* w, void* stream);
 
 /* Hyper-parameters of the Cartesian sampler (Sec. 4.3), host-only (no
  * device work, no context): with g(x) = int_0^x f W(f) F(f)^2 df (F the

@@ -166,6 +166,8 @@ def load_library():
         "qrfs_sample_frequencies": (S, [_P, ctypes.POINTER(Sampler), _I64, _I64, _P, _P, _P, _P]),
         "qrfs_weights": (S, [_P, ctypes.POINTER(Psd), ctypes.POINTER(Aperture), _I64, _P, _P, _P,
                              _P, _P]),
+        "qrfs_sample_weights": (S, [_P, ctypes.POINTER(Sampler), _I64, _I64, ctypes.POINTER(Psd),
+                                    ctypes.POINTER(Aperture), _P, _P, _P, _P]),
         "qrfs_synthesize_phase": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _I64, _I64,
                                       ctypes.POINTER(Rng), _P, _I32, _P, _P]),
         "qrfs_piston": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _I64,
@@ -300,6 +302,19 @@ class Context:
         _check(load_library().qrfs_sample_frequencies(self._h, ctypes.byref(sampler), n_sets, K,
                                                       _ptr(fx), _ptr(fy), _ptr(area), _stream()))
         return fx, fy, area
+
+    def sample_weights(self, sampler, n_sets, K, psd_, aperture=None):
+        """Sampling and weights in one pass (no cell areas); returns
+        (fx, fy, w) float64 [n_sets*K]; advances sampler.index."""
+        n = n_sets * K
+        fx = torch.empty(n, dtype=torch.float64, device=self.device)
+        fy = torch.empty_like(fx)
+        w = torch.empty_like(fx)
+        ap = ctypes.byref(aperture) if aperture is not None else None
+        _check(load_library().qrfs_sample_weights(self._h, ctypes.byref(sampler), n_sets, K,
+                                                  ctypes.byref(psd_), ap, _ptr(fx), _ptr(fy),
+                                                  _ptr(w), _stream()))
+        return fx, fy, w
 
     def weights(self, psd_, fx, fy, area, aperture=None):
         n = fx.numel()

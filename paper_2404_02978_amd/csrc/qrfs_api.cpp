@@ -172,6 +172,25 @@ hipError_t sample_any(const qrfs_sampler* s, uint64_t index, int64_t n_sets, int
                                s->fmin, s->fmax, fx, fy, area, st);
 }
 
+// Frequencies and weights of n_sets sets for a pipeline that needs no cell
+// areas: one fused kernel for the R2, pseudo-random and jittered samplers;
+// the learned sampler writes its areas to `area` and the weights follow.
+hipError_t sample_weights_any(const qrfs_sampler* s, uint64_t index, int64_t n_sets, int64_t K,
+                              const qrfs_psd* psd, double c, const qrfs_aperture* ap, double* fx,
+                              double* fy, double* area, double* w, hipStream_t st) {
+    const int has_ap = ap ? 1 : 0;
+    const double D = ap ? ap->D : 0.0, d = ap ? ap->d : 0.0;
+    if (s->scheme == QRFS_SAMPLER_LEARNED) {
+        hipError_t e = sample_any(s, index, n_sets, K, fx, fy, area, st);
+        if (e != hipSuccess) return e;
+        return qrfs::launch_weights(psd->model, c, psd->r0, psd->L0, has_ap, D, d, n_sets * K, fx,
+                                    fy, area, w, st);
+    }
+    return qrfs::launch_sample_weights(s->scheme, s->seed_x, s->seed_y, index, n_sets, K, s->N,
+                                       s->df, s->fmin, s->fmax, psd->model, c, psd->r0, psd->L0,
+                                       has_ap, D, d, fx, fy, w, st);
+}
+
 // Runs launch_sum over all sets, splitting the grid so no launch exceeds
 // 2^30 blocks.
 qrfs_status run_sum(int precision, int basis, int epi, qrfs::SumArgs a, int64_t n_sets,
@@ -465,6 +484,37 @@ qrfs_status qrfs_weights(qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aper
     return ok();
 }
 
+qrfs_status qrfs_sample_weights(qrfs_context* ctx, qrfs_sampler* s, int64_t n_sets, int64_t K,
+                                const qrfs_psd* psd, const qrfs_aperture* ap, double* fx,
+                                double* fy, double* w, void* stream) {
+    qrfs_status st = check_sampler(s, K);
+    if (st) return st;
+    if ((st = check_psd(psd))) return st;
+    if (ap && (st = check_ap(ap))) return st;
+    if (K <= 0 || n_sets <= 0)
+        return fail(QRFS_ERR_INVALID_ARG, "K and n_sets must be > 0 (got %lld, %lld)",
+                    (long long)K, (long long)n_sets);
+    if (n_sets > INT64_MAX / K || n_sets * K > ((int64_t)1 << 40))
+        return fail(QRFS_ERR_INVALID_ARG, "n_sets * K too large");
+    CHECK_PTR(fx);
+    CHECK_PTR(fy);
+    CHECK_PTR(w);
+    if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
+    double* area = nullptr;
+    if (s->scheme == QRFS_SAMPLER_LEARNED) {  // its cell areas go through the workspace
+        if ((st = ensure_workspace(ctx, (size_t)(n_sets * K) * sizeof(double)))) return st;
+        area = (double*)ctx->ws;
+    }
+    const double c = psd->c > 0.0 ? psd->c : qrfs::kPsdConstant;
+    hipError_t e =
+        sample_weights_any(s, s->index, n_sets, K, psd, c, ap, fx, fy, area, w, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sampler / weights launch");
+    s->index += (uint64_t)(n_sets * K);
+    return ok();
+}
+
 qrfs_status qrfs_synthesize_phase(qrfs_context* ctx, int64_t K, const double* fx,
                                   const double* fy, const double* w, int64_t P,
                                   const double* px, const double* py, int64_t R,
@@ -549,11 +599,9 @@ qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
     for (int64_t s0 = 0; s0 < n_sets; s0 += spb) {
         int64_t s1 = s0 + spb < n_sets ? s0 + spb : n_sets;
         int64_t ns = s1 - s0;
-        hipError_t e = sample_any(s, s->index + (uint64_t)(s0 * K), ns, K, fx, fy, area, stream_);
-        if (e != hipSuccess) return hip_fail(e, "sampler launch");
-        e = qrfs::launch_weights(psd->model, c, psd->r0, psd->L0, 1, ap->D, ap->d, ns * K, fx, fy,
-                                 area, w, stream_);
-        if (e != hipSuccess) return hip_fail(e, "weights launch");
+        hipError_t e = sample_weights_any(s, s->index + (uint64_t)(s0 * K), ns, K, psd, c, ap, fx,
+                                          fy, area, w, stream_);
+        if (e != hipSuccess) return hip_fail(e, "sampler / weights launch");
         qrfs::SumArgs a{};
         a.K = K;
         a.fx = fx;
@@ -745,12 +793,10 @@ qrfs_status qrfs_temporal_piston_structure(qrfs_context* ctx, const qrfs_psd* ps
         const int64_t ns = s1 - s0;
         const int64_t r0 = s0 * R_block;
         const int64_t rows = (s1 * R_block < R ? s1 * R_block : R) - r0;
-        e = sample_any(s, s->index + (uint64_t)(s0 * K), ns, K, fx, fy, area, stream_);
-        if (e != hipSuccess) return hip_fail(e, "sampler launch");
         // equal apertures: the filter of Eq. 7 folds into the weight
-        e = qrfs::launch_weights(psd->model, c, psd->r0, psd->L0, 1, ap->D, ap->d, ns * K, fx, fy,
-                                 area, w, stream_);
-        if (e != hipSuccess) return hip_fail(e, "weights launch");
+        e = sample_weights_any(s, s->index + (uint64_t)(s0 * K), ns, K, psd, c, ap, fx, fy, area,
+                               w, stream_);
+        if (e != hipSuccess) return hip_fail(e, "sampler / weights launch");
         // the piece as a problem of its own: realisations r0 .. r0 + rows
         qrfs::SumArgs a{};
         a.K = K;

@@ -7,17 +7,18 @@
 namespace qrfs {
 
 // ------------------------------------------------------------- sampler ----
-// One thread per frequency.  Point n = index + 1 + i of the R2 sequence
+// Frequency i of a launch.  Point n = index + 1 + i of the R2 sequence
 // (Sec. 3.2, Eq. 6) for schemes 0, 1, 3, of the pseudo-random stream for
 // schemes 4-7 (the randomised samplers of Sec. 3.1), mapped by Eq. 5
 // (Cartesian: schemes 0, 5), the log-polar map (1, 6), the square-to-disc
 // map (3, 7), or placed in its cell of the jittered grid of Eq. 4 (4).
-__global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n,
-                         int64_t K, int32_t N, double df, double L, double fmin, double lr,
-                         double* __restrict__ fx, double* __restrict__ fy,
-                         double* __restrict__ area) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__device__ __forceinline__ void sample_one(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
+                                           int64_t i, int64_t K, int32_t N, double df, double L,
+                                           double fmin, double lr, double& fx, double& fy,
+                                           double& area) {
+    // no fused multiply-adds here or in weight_one: the values then do not
+    // depend on the kernel they are inlined into
+#pragma clang fp contract(off)
     double ux, uy;
     if (scheme >= 4)
         pseudo_point(s0x, s0y, index + 1u + (uint64_t)i, ux, uy);
@@ -25,9 +26,9 @@ __global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
         r2_point(s0x, s0y, index + 1u + (uint64_t)i, ux, uy);
     const int map = scheme >= 5 ? (scheme == 7 ? 3 : scheme - 5) : scheme;
     if (map == 0) {
-        fx[i] = L * (ux - 0.5);
-        fy[i] = L * (uy - 0.5);
-        area[i] = L * L / (double)K;
+        fx = L * (ux - 0.5);
+        fy = L * (uy - 0.5);
+        area = L * L / (double)K;
     } else if (map == 4) {
         // Eq. 4: point k = iy N + ix of a set (K = N^2) at its cell's lower
         // corner -N df / 2 + i df plus the jitter u df, as df (i + u - N/2)
@@ -35,9 +36,9 @@ __global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
         const int64_t k = i % K;
         const double ix = (double)(k % N), iy = (double)(k / N);
         const double h = 0.5 * (double)N;
-        fx[i] = df * (ix + ux - h);
-        fy[i] = df * (iy + uy - h);
-        area[i] = df * df;
+        fx = df * (ix + ux - h);
+        fy = df * (iy + uy - h);
+        area = df * df;
     } else if (map == 3) {
         // polar quasi-random frequencies (Sec. 3.2): concentric square-to-
         // disc map of the point, disc radius L, equal cell areas
@@ -52,17 +53,30 @@ __global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
         }
         double s, c;
         sincospi(ang, &s, &c);
-        fx[i] = L * rad * c;
-        fy[i] = L * rad * s;
-        area[i] = 3.141592653589793 * L * L / (double)K;
+        fx = L * rad * c;
+        fy = L * rad * s;
+        area = 3.141592653589793 * L * L / (double)K;
     } else {
         double f = fmin * exp(lr * ux);
         double s, c;
         sincospi(2.0 * uy, &s, &c);
-        fx[i] = f * c;
-        fy[i] = f * s;
-        area[i] = 2.0 * 3.141592653589793 * lr * f * f / (double)K;
+        fx = f * c;
+        fy = f * s;
+        area = 2.0 * 3.141592653589793 * lr * f * f / (double)K;
     }
+}
+
+__global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n,
+                         int64_t K, int32_t N, double df, double L, double fmin, double lr,
+                         double* __restrict__ fx, double* __restrict__ fy,
+                         double* __restrict__ area) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x, y, ar;
+    sample_one(scheme, s0x, s0y, index, i, K, N, df, L, fmin, lr, x, y, ar);
+    fx[i] = x;
+    fy[i] = y;
+    area[i] = ar;
 }
 
 // ------------------------------------------------------------- weights ----
@@ -72,18 +86,42 @@ __global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
 // exponent's absolute error is a few ulps of |log2 q| <= ~40, so w is within
 // ~2e-15 relative of the correctly rounded value, and the kernel skips the
 // exactness work of a general pow and one square root.
+__device__ __forceinline__ double weight_one(int model, double c, double r0_m53, double inv_L02,
+                                             int has_ap, double D, double d, double x, double y,
+                                             double area) {
+#pragma clang fp contract(off)
+    const double f2 = x * x + y * y;
+    const double q = f2 + (model == 1 ? inv_L02 : 0.0);
+    double v = q == 0.0 ? 0.0 : exp2(-11.0 / 12.0 * log2(q)) * sqrt(c * r0_m53 * area);
+    if (has_ap) v *= aperture_filter(D, d, sqrt(f2));
+    return v;
+}
+
 __global__ void k_weights(int model, double c, double r0_m53, double inv_L02, int has_ap,
                           double D, double d, int64_t n, const double* __restrict__ fx,
                           const double* __restrict__ fy, const double* __restrict__ area,
                           double* __restrict__ w) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double x = fx[i], y = fy[i];
-    const double f2 = x * x + y * y;
-    const double q = f2 + (model == 1 ? inv_L02 : 0.0);
-    double v = q == 0.0 ? 0.0 : exp2(-11.0 / 12.0 * log2(q)) * sqrt(c * r0_m53 * area[i]);
-    if (has_ap) v *= aperture_filter(D, d, sqrt(f2));
-    w[i] = v;
+    w[i] = weight_one(model, c, r0_m53, inv_L02, has_ap, D, d, fx[i], fy[i], area[i]);
+}
+
+// Both in one pass, for pipelines that need the weights but not the cell
+// areas: the same values as k_sample followed by k_weights, without writing
+// and re-reading the areas and the frequencies.
+__global__ void k_sample_weights(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
+                                 int64_t n, int64_t K, int32_t N, double df, double L,
+                                 double fmin, double lr, int model, double c, double r0_m53,
+                                 double inv_L02, int has_ap, double D, double d,
+                                 double* __restrict__ fx, double* __restrict__ fy,
+                                 double* __restrict__ w) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x, y, ar;
+    sample_one(scheme, s0x, s0y, index, i, K, N, df, L, fmin, lr, x, y, ar);
+    fx[i] = x;
+    fy[i] = y;
+    w[i] = weight_one(model, c, r0_m53, inv_L02, has_ap, D, d, x, y, ar);
 }
 
 // ----------------------------------------------------------- launchers ----
@@ -97,6 +135,22 @@ hipError_t launch_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
     double lr = (scheme == 1 || scheme == 6) ? log(fmax / fmin) : 0.0;
     hipLaunchKernelGGL(k_sample, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, scheme, s0x, s0y,
                        index, n, K, N, df, L, fmin, lr, fx, fy, area);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_weights(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
+                                 int64_t n_sets, int64_t K, int32_t N, double df, double fmin,
+                                 double fmax, int model, double c, double r0, double L0,
+                                 int has_ap, double D, double d, double* fx, double* fy,
+                                 double* w, hipStream_t st) {
+    int64_t n = n_sets * K;
+    double L = (scheme == 3 || scheme == 7) ? fmax : (double)N * df;
+    double lr = (scheme == 1 || scheme == 6) ? log(fmax / fmin) : 0.0;
+    double r0_m53 = pow(r0, -5.0 / 3.0);
+    double inv_L02 = model == 1 ? 1.0 / (L0 * L0) : 0.0;
+    hipLaunchKernelGGL(k_sample_weights, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, scheme,
+                       s0x, s0y, index, n, K, N, df, L, fmin, lr, model, c, r0_m53, inv_L02,
+                       has_ap, D, d, fx, fy, w);
     return hipGetLastError();
 }
 

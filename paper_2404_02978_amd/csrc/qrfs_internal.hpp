@@ -159,6 +159,14 @@ hipError_t launch_weights(int model, double c, double r0, double L0, int has_ap,
                           double d, int64_t n, const double* fx, const double* fy,
                           const double* area, double* w, hipStream_t st);
 
+// launch_sample followed by launch_weights in one kernel (the same values),
+// writing the frequencies and the weights but not the cell areas.
+hipError_t launch_sample_weights(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
+                                 int64_t n_sets, int64_t K, int32_t N, double df, double fmin,
+                                 double fmax, int model, double c, double r0, double L0,
+                                 int has_ap, double D, double d, double* fx, double* fy,
+                                 double* w, hipStream_t st);
+
 // Frozen-flow temporal structure function (time series of M <= 4096 points).
 constexpr int TEMPORAL_MAX_M = 4096;
 constexpr int TEMPORAL_ROWS_PER_BLOCK = 8;

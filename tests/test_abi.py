@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(q):
 
 def test_abi_version_and_strings(q):
     lib = q.load_library()
-    assert lib.qrfs_abi_version() == 2
+    assert lib.qrfs_abi_version() == 3
     assert lib.qrfs_error_string(0) == b"success"
     assert lib.qrfs_error_string(-1) == b"invalid argument"
     assert lib.qrfs_error_string(-4) == b"unsupported"

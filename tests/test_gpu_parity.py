@@ -358,6 +358,38 @@ def test_invalid_arguments_raise(q, ctx):
     assert e.value.status == q.ERR_INVALID_ARG
 
 
+@pytest.mark.parametrize("scheme", ["cartesian", "disc", "jitter", "random_logpolar",
+                                    "random_cartesian", "random_disc"])
+def test_end_to_end_sampler_and_weights_equal_separate_calls(q, ctx, scheme):
+    """The end-to-end structure function draws frequencies and weights in one
+    fused kernel; with the same sets drawn by qrfs_sample_frequencies and
+    weighted by qrfs_weights, the set-level entry gives bit-identical
+    results, for every sampler the fused kernel serves."""
+    cfg = workloads.diffpiston()
+    N, df = 44, 0.25 / 22
+    K, R, R_block = N * N, 300, 64
+    n_sets = math.ceil(R / R_block)
+    make = {
+        "cartesian": lambda: q.cartesian_sampler(N, df, index=11),
+        "disc": lambda: q.disc_sampler(0.25, index=11),
+        "jitter": lambda: q.jitter_sampler(N, df, index=11),
+        "random_logpolar": lambda: q.random_sampler(q.SAMPLER_RANDOM_LOGPOLAR, fmin=1e-3,
+                                                    fmax=1e2, index=11),
+        "random_cartesian": lambda: q.random_sampler(q.SAMPLER_RANDOM_CARTESIAN, N=N, df=df,
+                                                     index=11),
+        "random_disc": lambda: q.random_sampler(q.SAMPLER_RANDOM_DISC, fmax=0.25, index=11),
+    }[scheme]
+    p, ap = q.psd(0.1, 22.0), q.Aperture(8.0, 1.1)
+    bx, by = dev(cfg["bx"]), dev(cfg["by"])
+    sf, se = ctx.diff_piston_structure(p, ap, bx, by, make(), K, R, R_block,
+                                       rng=q.Rng(5, 2, 0), precision=1)
+    fx, fy, area = ctx.sample_frequencies(make(), n_sets, K)
+    w = ctx.weights(p, fx, fy, area, ap)
+    sf2, se2 = ctx.diff_piston_structure_sets(K, fx, fy, w, bx, by, R, R_block,
+                                              rng=q.Rng(5, 2, 0), precision=1)
+    assert torch.equal(sf, sf2) and torch.equal(se, se2)
+
+
 @pytest.mark.parametrize("precision", PRECS)
 def test_diff_piston_structure_sets_equals_end_to_end(q, ctx, precision):
     """The set-level entry gives bit-identical results to the end-to-end one

@@ -146,6 +146,21 @@ def test_learned_sampler_parity(q, ctx):
     p.close()
 
 
+def test_learned_sample_weights_equal_two_calls(q, ctx):
+    """The learned sampler through qrfs_sample_weights (cell areas in the
+    context's workspace) gives the values of the two separate calls."""
+    tab = _oracle_table()
+    p = q.Proposal(ctx, FMIN, FMAX, np.zeros(q.PROPOSAL_NPARAM, dtype=np.float32))
+    p.set_table(*[dev(x) for x in tab])
+    psd, ap = q.psd(0.1, 25.0), q.Aperture(1.8, 0.0)
+    fx, fy, w = ctx.sample_weights(q.learned_sampler(p, index=5), 2, 777, psd, ap)
+    fx2, fy2, area = ctx.sample_frequencies(q.learned_sampler(p, index=5), 2, 777)
+    w2 = ctx.weights(psd, fx2, fy2, area, ap)
+    torch.cuda.synchronize()
+    assert torch.equal(fx, fx2) and torch.equal(fy, fy2) and torch.equal(w, w2)
+    p.close()
+
+
 @pytest.mark.parametrize("precision", [0, 3])
 def test_learned_structure_function_parity(q, ctx, precision):
     cfg = workloads.diffpiston()

@@ -173,3 +173,45 @@ def test_sampling_error_ordering(q, ctx):
         spread[name] = S.std(axis=0) / S.mean(axis=0)
         print(name, "relative spread of S per baseline", np.round(spread[name], 5))
     assert np.all(spread["r2"] < spread["jitter"]) and np.all(spread["jitter"] < spread["random"])
+
+
+# ------------------------------------------------- sampling + weights ----
+
+@pytest.mark.parametrize("scheme", ["cartesian", "logpolar", "disc", "jitter", "random_logpolar",
+                                    "random_cartesian", "random_disc"])
+@pytest.mark.parametrize("ap", [None, (8.0, 1.1)])
+def test_sample_weights_equal_two_calls(q, ctx, scheme, ap):
+    """qrfs_sample_weights (one fused kernel) gives exactly the frequencies
+    and weights of qrfs_sample_frequencies followed by qrfs_weights, and
+    advances the sampler the same way."""
+    N, df, n_sets = 44, 0.25 / 22, 3
+    K = N * N
+    make = {
+        "cartesian": lambda: q.cartesian_sampler(N, df, index=9),
+        "logpolar": lambda: q.logpolar_sampler(1e-3, 1e2, index=9),
+        "disc": lambda: q.disc_sampler(0.25, index=9),
+        "jitter": lambda: q.jitter_sampler(N, df, index=9),
+        "random_logpolar": lambda: q.random_sampler(q.SAMPLER_RANDOM_LOGPOLAR, fmin=1e-3,
+                                                    fmax=1e2, index=9),
+        "random_cartesian": lambda: q.random_sampler(q.SAMPLER_RANDOM_CARTESIAN, N=N, df=df,
+                                                     index=9),
+        "random_disc": lambda: q.random_sampler(q.SAMPLER_RANDOM_DISC, fmax=0.25, index=9),
+    }[scheme]
+    p = q.psd(0.1, 22.0)
+    aperture = None if ap is None else q.Aperture(*ap)
+    s1, s2 = make(), make()
+    fx, fy, w = ctx.sample_weights(s1, n_sets, K, p, aperture)
+    fx2, fy2, area = ctx.sample_frequencies(s2, n_sets, K)
+    w2 = ctx.weights(p, fx2, fy2, area, aperture)
+    torch.cuda.synchronize()
+    assert s1.index == s2.index == 9 + n_sets * K
+    assert torch.equal(fx, fx2) and torch.equal(fy, fy2) and torch.equal(w, w2)
+
+
+def test_sample_weights_rejects_bad_arguments(q, ctx):
+    with pytest.raises(q.QrfsError) as e:
+        ctx.sample_weights(q.logpolar_sampler(2.0, 1.0), 1, 8, q.psd(0.1, 25.0))
+    assert e.value.status == q.ERR_INVALID_ARG
+    with pytest.raises(q.QrfsError) as e:
+        ctx.sample_weights(q.logpolar_sampler(1e-3, 1e2), 1, 8, q.psd(-0.1, 25.0))
+    assert e.value.status == q.ERR_INVALID_ARG
