@@ -117,11 +117,11 @@ def plain_vs_chosen(q, ctx, cfg, L0=25.0, R=100000, R_block=256):
     an = analytic.sf_band(cfg["bx"], cfg["r0"], L0, cfg["fmin"], cfg["fmax"], D=cfg["D"])
 
     t0 = time.perf_counter()
-    c4 = torch.as_tensor(workloads.proposal_contexts(128, seed=0), device=dev)
+    ctxs = torch.as_tensor(workloads.proposal_contexts(128, seed=0), device=dev)
     prop = q.Proposal(ctx, cfg["fmin"], cfg["fmax"], workloads.mlp_init(0).astype(np.float32))
     plain_rows = q.logpolar_sampler(cfg["fmin"], cfg["fmax"], index=1 << 40)
-    ell, theta, h = prop.rows(plain_rows, c4, 2048, cfg["r0"])
-    loss = prop.train(c4, ell, theta, h, steps=600, ctx_per_step=16, lr=2e-3, seed=1)
+    ell, theta, h = prop.rows(plain_rows, ctxs, 2048, cfg["r0"])
+    loss = prop.train(ctxs, ell, theta, h, steps=600, ctx_per_step=16, lr=2e-3, seed=1)
     prop.tabulate(cfg["D"], L0, cfg["bx"], np.zeros(cfg["bx"].size))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
