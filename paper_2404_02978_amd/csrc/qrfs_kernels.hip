@@ -892,7 +892,7 @@ __global__ void k_reset_counter(unsigned* counter) {
 // columns.  Adds the K-range partial sums of each differential piston in a
 // fixed order, then accumulates its square and fourth power per column over
 // the block's rows; the 8 row groups are combined in a fixed order.
-constexpr int SF_ROWS = 256;
+constexpr int SF_ROWS = 64;  // rows per block: ~1600 blocks for 1e5 rows, enough to hide load latency
 
 __global__ __launch_bounds__(256) void k_sfsum_rows(const float* __restrict__ phi, int ksplit,
                                                     int64_t R, int64_t P,
