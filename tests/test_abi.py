@@ -101,6 +101,26 @@ def test_argument_checks_precede_device_use(q):
                                         ctypes.byref(q.logpolar_sampler(1e-3, 1e2)), 8, 10, 10,
                                         ctypes.byref(rng), 1, p, None, None)
     assert st == q.ERR_INVALID_ARG
+    # fused sampling + weights: bad sampler, bad PSD, bad aperture, NULL output,
+    # then valid arguments reaching the NULL context (sampler index untouched)
+    s = q.logpolar_sampler(2.0, 1.0)
+    st = lib.qrfs_sample_weights(None, ctypes.byref(s), 1, 8, ctypes.byref(q.psd(0.1, 25.0)),
+                                 None, p, p, p, None)
+    assert st == q.ERR_INVALID_ARG
+    s = q.logpolar_sampler(1e-3, 1e2, index=5)
+    st = lib.qrfs_sample_weights(None, ctypes.byref(s), 1, 8, ctypes.byref(q.psd(0.1, -1.0)),
+                                 None, p, p, p, None)
+    assert st == q.ERR_INVALID_ARG and b"L0" in lib.qrfs_last_error_detail()
+    st = lib.qrfs_sample_weights(None, ctypes.byref(s), 1, 8, ctypes.byref(q.psd(0.1, 25.0)),
+                                 ctypes.byref(q.Aperture(1.0, 1.0)), p, p, p, None)
+    assert st == q.ERR_INVALID_ARG
+    st = lib.qrfs_sample_weights(None, ctypes.byref(s), 1, 8, ctypes.byref(q.psd(0.1, 25.0)),
+                                 None, p, p, None, None)
+    assert st == q.ERR_INVALID_ARG
+    st = lib.qrfs_sample_weights(None, ctypes.byref(s), 1, 8, ctypes.byref(q.psd(0.1, 25.0)),
+                                 None, p, p, p, None)
+    assert st == q.ERR_INVALID_ARG and b"context" in lib.qrfs_last_error_detail()
+    assert s.index == 5
     # valid arguments, NULL context
     st = lib.qrfs_synthesize_phase(None, 10, p, p, p, 4, p, p, 5, 5, ctypes.byref(rng), None, 1,
                                    p, None)
