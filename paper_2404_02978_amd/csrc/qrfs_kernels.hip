@@ -694,21 +694,21 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
                                 av[m][mw][q], bv[nb][q], acc[mw][nb], 0, 0, 0);
             }
         } else {
-            bf16x8 ap[KC / 8][MW][NPL];
+            // each group of 8 contraction values draws its coefficients right
+            // before its MFMAs: the generator's vector work runs beside the
+            // matrix cores, and only one group's operand planes are live
+            __syncthreads();
 #pragma unroll
             for (int sg = 0; sg < KC / 8; ++sg) {
                 const uint32_t t = (uint32_t)(k0 / 2) + 4u * sg + 2u * (uint32_t)lh;
+                bf16x8 ap[MW][NPL];
 #pragma unroll
                 for (int mw = 0; mw < MW; ++mw) {
                     float g[8];
                     coef4_src<CSRC>(a, myrow[mw], rowok[mw], t, g);
                     coef4_src<CSRC>(a, myrow[mw], rowok[mw], t + 1u, g + 4);
-                    split8_bf16<NPL>(g, ap[sg][mw]);
+                    split8_bf16<NPL>(g, ap[mw]);
                 }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int sg = 0; sg < KC / 8; ++sg) {
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     const int off = buf * NT * STR_H + (nb * 32 + lr) * STR_H + 16 * sg + 8 * lh;
@@ -720,13 +720,13 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
                         f32x16 c = acc[mw][nb];
                         // smallest products first
                         if constexpr (NPL == 3) {
-                            c = mfma_bf16(ap[sg][mw][2], bp[0], c);
-                            c = mfma_bf16(ap[sg][mw][1], bp[1], c);
-                            c = mfma_bf16(ap[sg][mw][0], bp[2], c);
+                            c = mfma_bf16(ap[mw][2], bp[0], c);
+                            c = mfma_bf16(ap[mw][1], bp[1], c);
+                            c = mfma_bf16(ap[mw][0], bp[2], c);
                         }
-                        c = mfma_bf16(ap[sg][mw][1], bp[0], c);
-                        c = mfma_bf16(ap[sg][mw][0], bp[1], c);
-                        c = mfma_bf16(ap[sg][mw][0], bp[0], c);
+                        c = mfma_bf16(ap[mw][1], bp[0], c);
+                        c = mfma_bf16(ap[mw][0], bp[1], c);
+                        c = mfma_bf16(ap[mw][0], bp[0], c);
                         acc[mw][nb] = c;
                     }
                 }
