@@ -82,17 +82,37 @@ __global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
 // ------------------------------------------------------------- weights ----
 // w = sqrt(W(|f|) area) [x F(|f|)], the amplitude of Eq. 3 (Eq. 7 filter),
 // with W = c r0^-5/3 q^-11/6, q = |f|^2 (+ L0^-2): evaluated as
-// q^-11/12 sqrt(c r0^-5/3 area), the power as exp2(-11/12 log2 q).  The
-// exponent's absolute error is a few ulps of |log2 q| <= ~40, so w is within
-// ~2e-15 relative of the correctly rounded value, and the kernel skips the
-// exactness work of a general pow and one square root.
+// q^-11/12 sqrt(c r0^-5/3 area), the power by pow_m11_12 (no general pow,
+// one square root fewer).
+// q^(-11/12) for q > 0 (the square root of the PSD's q^(-11/6)): q = 2^(12k) r
+// exactly with r in [2^-6, 2^6); a binary32 estimate of r^(-11/12) from the
+// hardware log2 / exp2 (relative error ~5e-7); two binary64 Newton steps on
+// y^12 r^11 = 1, y <- y (1 + (1 - y^12 r^11) / 12), each squaring the
+// relative error (to ~6e-13, then rounding); rescaled by 2^(-11k).  Within
+// ~3e-16 of the exact power of the rational exponent.
+__device__ __forceinline__ double pow_m11_12(double q) {
+    const int e = ilogb(q);
+    const int k = (e + 6 + 1200) / 12 - 100;  // floor((e + 6) / 12)
+    const double r = ldexp(q, -12 * k);
+    const float rf = (float)r;
+    double y = (double)__builtin_amdgcn_exp2f(-0.9166666865f * __builtin_amdgcn_logf(rf));
+    const double r2 = r * r, r4 = r2 * r2, r11 = (r4 * r4) * (r2 * r);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double y2 = y * y, y4 = y2 * y2;
+        const double t = ((y4 * y4) * y4) * r11;
+        y = fma(y, (1.0 - t) * (1.0 / 12.0), y);
+    }
+    return ldexp(y, -11 * k);
+}
+
 __device__ __forceinline__ double weight_one(int model, double c, double r0_m53, double inv_L02,
                                              int has_ap, double D, double d, double x, double y,
                                              double area) {
 #pragma clang fp contract(off)
     const double f2 = x * x + y * y;
     const double q = f2 + (model == 1 ? inv_L02 : 0.0);
-    double v = q == 0.0 ? 0.0 : exp2(-11.0 / 12.0 * log2(q)) * sqrt(c * r0_m53 * area);
+    double v = q == 0.0 ? 0.0 : pow_m11_12(q) * sqrt(c * r0_m53 * area);
     if (has_ap) v *= aperture_filter(D, d, sqrt(f2));
     return v;
 }
