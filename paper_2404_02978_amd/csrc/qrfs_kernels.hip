@@ -439,8 +439,17 @@ __global__ __launch_bounds__(256) void k_sum_f32n(SumArgs a, int64_t col_tiles) 
 // waves in order), and the block writes dp^2 and dp^4 as the set's partial
 // sums.  T = float: the FP32 path's coefficients and basis; T = double:
 // the FP64 path's.
+// The binary32 variant for up to 32 baselines asks for five waves per SIMD:
+// the compiler then fits it in 84 VGPRs without spills (119 by default) and
+// the extra wave hides more of the sine and FP64 latency.
+template <typename T, int NPM>
+constexpr int sf_one_min_waves() {
+    return (sizeof(T) == 4 && NPM == 32) ? 5 : 1;
+}
+
 template <typename T, int NPM, int CSRC>
-__global__ __launch_bounds__(256) void k_sf_one(SumArgs a) {
+__global__ __launch_bounds__(256) __attribute__((
+    amdgpu_waves_per_eu(sf_one_min_waves<T, NPM>(), 8))) void k_sf_one(SumArgs a) {
     __shared__ double2 sB[NPM];
     __shared__ double red[4][NPM];
     const int tid = threadIdx.x;
