@@ -338,6 +338,48 @@ def test_diff_piston_structure_full_size(q, ctx, R_block):
     assert np.all(np.abs(z) < 4.5)
 
 
+def test_diff_piston_structure_sets_full_size_bf16x6(q, ctx):
+    """The benchmark's own launch sequence at full size: 1e5 realisations,
+    K = 16384, 32 baselines, R_block = 256, BF16x6, the frequency sets and
+    weights drawn in one pass and the sums taken from those sets.  (a) The
+    fused structure-function sums equal the mean squares of the stored
+    differential pistons of the same sets and coefficients; (b) sampled
+    realisations of those pistons equal the oracle's within the BF16x6
+    tolerance; (c) the estimate agrees with the analytic curve within its
+    statistical error."""
+    from oracle import analytic as A
+    cfg = workloads.diffpiston()
+    K, R, R_block = cfg["K"], cfg["R"], 256
+    n_sets = math.ceil(R / R_block)
+    p = q.psd(cfg["r0"], 25.0)
+    ap = q.Aperture(cfg["D"], 0.0)
+    bx, by = dev(cfg["bx"]), dev(cfg["by"])
+    s = q.logpolar_sampler(cfg["fmin"], cfg["fmax"])
+    fx, fy, w = ctx.sample_weights(s, n_sets, K, p, ap)
+    assert s.index == n_sets * K
+    rng = q.Rng(0, 0, q.COEF_GAUSS_CS)
+    sf, se = ctx.diff_piston_structure_sets(K, fx, fy, w, bx, by, R, R_block, rng=rng,
+                                            precision=q.PREC_BF16X6)
+    dp = ctx.diff_piston(K, fx, fy, w, bx, by, R, R_block, rng=rng, precision=q.PREC_BF16X6)
+    dph = host(dp)
+    mean_sq = np.mean(dph * dph, axis=0)
+    assert np.max(np.abs(host(sf) / mean_sq - 1)) < 1e-6
+    px = np.concatenate([[0.0], cfg["bx"]])
+    py = np.concatenate([[0.0], cfg["by"]])
+    for r in (0, 255, 256, 77777, R - 1):
+        sl = slice((r // R_block) * K, (r // R_block + 1) * K)
+        pist = oracle.synthesize(host(fx[sl]), host(fy[sl]), host(w[sl]), px, py, 1, 1, K=K,
+                                 seed=0, counter=r)
+        ref = pist[0, 1:] - pist[0, 0]
+        e = np.max(np.abs(dph[r] - ref)) / math.sqrt(np.mean(ref * ref))
+        print(f"row {r}: eps_max {e:.3e}")
+        assert e < TOL[q.PREC_BF16X6]
+    an = A.sf_band(cfg["bx"], cfg["r0"], 25.0, cfg["fmin"], cfg["fmax"], D=cfg["D"])
+    z = (host(sf) - an) / host(se)
+    print("z", np.round(z, 2))
+    assert np.all(np.abs(z) < 4.5)
+
+
 # -------------------------------------------------------------- errors ----
 
 def test_invalid_arguments_raise(q, ctx):
