@@ -127,6 +127,57 @@ def test_batch_autotune(q, ctx):
     b.close()
 
 
+@pytest.mark.parametrize("precision", [3, 2])
+def test_batch_full_size_graph(q, ctx, precision):
+    """The 64 uneven instances of the benchmark (R = 256 each, K up to 65536,
+    grids up to 512^2 masked to the disk) in its timed configuration:
+    autotuned, then replayed from a HIP graph.  Two replays equal the eager
+    result bit for bit; the first and last eight rows of three instances
+    (largest K, most points, fewest points) agree with the oracle at 256
+    sampled points."""
+    specs = workloads.batched()
+    inst = []
+    for i, d in enumerate(specs):
+        inst.append(dict(psd=q.psd(d["r0"], d["L0"]),
+                         sampler=q.logpolar_sampler(workloads.FMIN, workloads.FMAX,
+                                                    index=i * (1 << 20)),
+                         K=d["K"], px=dev(d["px"]), py=dev(d["py"]), R=d["R"], R_block=d["R"],
+                         rng=q.Rng(d["seed"], d["counter"], q.COEF_GAUSS_CS)))
+    b = q.Batch(ctx, inst, precision=precision)
+    try:
+        b.autotune()
+        eager = [o.clone() for o in b.execute()]
+        torch.cuda.synchronize()
+        for rep in range(2):
+            for o in b.outputs:
+                o.fill_(float("nan"))
+            b.execute(use_graph=True)
+            torch.cuda.synchronize()
+            for o, e in zip(b.outputs, eager):
+                assert torch.equal(o, e), rep
+        sizes = [d["px"].size for d in specs]
+        picks = {int(np.argmax([d["K"] for d in specs])), int(np.argmax(sizes)),
+                 int(np.argmin(sizes))}
+        for j in sorted(picks):
+            d = specs[j]
+            fx, fy, area = oracle.sample_logpolar(1, d["K"], workloads.FMIN, workloads.FMAX,
+                                                  index=j * (1 << 20))
+            w = oracle.weights(fx, fy, area, r0=d["r0"], L0=d["L0"])
+            cols = np.random.default_rng(j).choice(d["px"].size, min(256, d["px"].size),
+                                                   replace=False)
+            ci = torch.as_tensor(cols, device="cuda")
+            for r0 in (0, d["R"] - 8):
+                ref = oracle.synthesize(fx, fy, w, d["px"][cols], d["py"][cols], 8, 8, K=d["K"],
+                                        seed=d["seed"], counter=d["counter"] + r0)
+                got = b.outputs[j][r0:r0 + 8][:, ci].double().cpu().numpy()
+                e = np.max(np.abs(got - ref)) / math.sqrt(np.mean(ref * ref))
+                print(f"p{precision} instance {j} (K {d['K']}, P {d['px'].size}) rows {r0}+: "
+                      f"eps_max {e:.3e}", flush=True)
+                assert e <= TOL[precision], (j, r0, e)
+    finally:
+        b.close()
+
+
 def test_batch_rejects_bad_instances(q, ctx):
     inst, _ = instances(q, 1)
     bad = dict(inst[0])
