@@ -3,7 +3,15 @@
   loss gradient        -- central finite differences of the loss itself
   forward              -- explicit numpy evaluation of the layer equations
   table                -- normalisation; a constant network gives the plain
-                          (uniform in ln f and angle) density
+                          (uniform in ln f and angle) density; closed forms
+                          of one-baseline and two-baseline tables built from
+                          networks with exactly known piecewise-constant
+                          outputs, and the mixture as a function of angle
+                          (tests/proposal_pins.py)
+  loss value           -- ln Lw for a constant network; closed-form log Z of
+                          a step network on the normaliser grid; the angular
+                          term at angles where its factor is 1 +- alpha or 1
+                          (tests/proposal_pins.py)
   learned sampler      -- reduces to the plain log-polar sampler for the
                           uniform table; with a trained-like table its 1/q
                           cell areas keep sum W dA unbiased (closed-form band
@@ -17,6 +25,7 @@ import pytest
 
 import oracle
 from oracle import analytic as A
+import proposal_pins as PP
 import workloads
 
 FMIN, FMAX = workloads.FMIN, workloads.FMAX
@@ -145,3 +154,13 @@ def test_training_rows_integrand():
         est = np.mean(h[c * m:(c + 1) * m]) * LW * 2 * np.pi
         an = A.sf_band([ctx[c, 2]], 0.1, ctx[c, 1], FMIN, FMAX, D=ctx[c, 0])[0]
         assert est == pytest.approx(an, rel=5e-3)
+
+
+@pytest.mark.parametrize("pin", PP.TABLE_PINS, ids=lambda f: f.__name__)
+def test_table_closed_forms(pin):
+    pin()
+
+
+@pytest.mark.parametrize("pin", PP.LOSS_PINS, ids=lambda f: f.__name__)
+def test_loss_value_closed_forms(pin):
+    pin()
