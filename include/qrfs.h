@@ -13,7 +13,9 @@
  *
  * Conventions for every entry point
  *   - Units: frequencies in cycles/m, positions in m, phase in rad at the
- *     wavelength r0 refers to (Sec. 4.1), structure functions in rad^2.
+ *     wavelength r0 refers to (Sec. 4.1), structure functions in rad^2;
+ *     with qrfs_psd.wavelength > 0 every output of the PSD-weighted sums is
+ *     optical path instead (m, m^2 for structure functions, Sec. 4.4).
  *   - Array arguments are DEVICE pointers (memory of the context's device),
  *     contiguous, naturally aligned, owned by the caller, unless the comment
  *     says "host".  Struct arguments are host pointers.
@@ -30,11 +32,15 @@
  *     R_block = 1 gives every realisation fresh frequencies, as the paper
  *     does (Sec. 3.2: the sequence is never reinitialised); R_block = R
  *     shares one set (the static sampling Sec. 2.3 warns about).
- *   - Random coefficients: Philox4x32-10 keyed by rng.seed, counter
- *     (block t, realisation lo32, realisation hi32, 0) with realisation =
- *     rng.counter + r; each 32-bit word gives u = ((x >> 8) + 1/2) 2^-24;
- *     Box-Muller of (u0,u1) and (u2,u3) gives coefficients c[4t..4t+3] with
- *     c[2k] = a_k, c[2k+1] = b_k (QRFS_COEF_GAUSS_CS).  QRFS_COEF_EQ3 uses
+ *   - Random coefficients: Philox4x32-10 (Salmon et al., SC'11) with key
+ *     (seed lo32, seed hi32) = rng.seed and counter (block t, realisation
+ *     lo32, realisation hi32, 0), realisation = rng.counter + r, gives the
+ *     words x0..x3 of block t; each word gives the uniform
+ *     u = ((x >> 9) + 1/2) 2^-23 = (2m + 1) 2^-24, m = x >> 9 (exact in
+ *     binary32, never 0 or 1); Box-Muller of (u0,u1) gives
+ *     c[4t] = sqrt(-2 ln u0) cos(2 pi u1), c[4t+1] = sqrt(-2 ln u0) sin(2 pi u1),
+ *     and of (u2,u3) likewise c[4t+2], c[4t+3], with c[2k] = a_k,
+ *     c[2k+1] = b_k (QRFS_COEF_GAUSS_CS).  QRFS_COEF_EQ3 uses
  *     block t = k: R_n = sqrt(-2 ln u0) cos(2 pi u1), R_u = u2,
  *     a = sqrt2 R_n cos(2 pi R_u), b = -sqrt2 R_n sin(2 pi R_u), which is the
  *     literal (2/sqrt2) R_n cos(2 pi (f.x + R_u)) term of Eq. 3.
@@ -62,8 +68,9 @@ typedef int32_t qrfs_status;
 #define QRFS_ERR_OUT_OF_MEMORY (-2) /* workspace allocation failed            */
 #define QRFS_ERR_DEVICE (-3)        /* HIP runtime error (launch, fault)      */
 #define QRFS_ERR_UNSUPPORTED (-4)   /* valid but not implemented combination  */
+#define QRFS_ERR_NOT_CONVERGED (-5) /* an iterative rule did not settle       */
 
-#define QRFS_ABI_VERSION 3
+#define QRFS_ABI_VERSION 4
 
 /* Static string for a status code. */
 QRFS_API const char* qrfs_error_string(qrfs_status s);
@@ -78,8 +85,16 @@ QRFS_API int32_t qrfs_abi_version(void);
  * destroy), tuned launch shapes. */
 typedef struct qrfs_context qrfs_context;
 
-/* Creates a context on HIP device `device`.  *out receives the handle. */
-QRFS_API qrfs_status qrfs_context_create(qrfs_context** out, int32_t device);
+/* Creates a context on HIP device `device`.  *out receives the handle.
+ * workspace_cap_bytes bounds the device workspace the context may hold
+ * (0: no bound).  A call whose workspace would exceed it fails with
+ * QRFS_ERR_OUT_OF_MEMORY before enqueueing anything; the two-phase kernel
+ * cuts its coefficient tiles into pieces that fit the cap when it can (at
+ * least one 256-row block of one set).  Batches allocate their own buffers
+ * (qrfs_batch_create) and are not bounded by it.
+ * Errors: out NULL; device out of range; no HIP device (QRFS_ERR_DEVICE). */
+QRFS_API qrfs_status qrfs_context_create(qrfs_context** out, int32_t device,
+                                         size_t workspace_cap_bytes);
 /* Synchronises the device and frees the workspace.  NULL is accepted. */
 QRFS_API qrfs_status qrfs_context_destroy(qrfs_context* ctx);
 
@@ -107,14 +122,25 @@ QRFS_API qrfs_status qrfs_context_set_tuning(qrfs_context* ctx, int32_t key, int
  *   von Karman  W(f) = c r0^(-5/3) (f^2 + L0^-2)^(-11/6)
  *   Kolmogorov  W(f) = c r0^(-5/3) f^(-11/3)     (L0 ignored; W(0) := 0)
  * c <= 0 selects Gamma(11/6)^2/(2 pi^(11/3)) (24/5 Gamma(6/5))^(5/6)
- * = 0.0228955871..., the value Eq. 7 prints as 0.02289. */
+ * = 0.0228955871..., the value Eq. 7 prints as 0.02289.
+ * r0 is the Fried parameter at the wavelength lambda of the light
+ * (Sec. 4.1: r0 = r0(lambda); it scales as lambda^(6/5), so a caller with
+ * r0 given at another wavelength converts it first).  wavelength = 0: phases
+ * in rad at that wavelength.  wavelength = lambda > 0 (m): optical path
+ * instead, phase times lambda / (2 pi), so every weight carries that factor
+ * and structure functions come out as D_OPD = (lambda / 2 pi)^2 D_phase in
+ * m^2 (Sec. 4.4).  Entry points that take a qrfs_psd apply it
+ * (qrfs_weights, qrfs_sample_weights, qrfs_diff_piston_structure,
+ * qrfs_temporal_piston_structure, batch instances, and the variance of
+ * qrfs_choose_cartesian). */
 #define QRFS_PSD_KOLMOGOROV 0
 #define QRFS_PSD_VON_KARMAN 1
 typedef struct {
     int32_t model;
     double c;
-    double r0; /* Fried parameter, m (> 0) */
-    double L0; /* outer scale, m (> 0 for von Karman) */
+    double r0;         /* Fried parameter at `wavelength`, m (> 0)      */
+    double L0;         /* outer scale, m (> 0 for von Karman)            */
+    double wavelength; /* m; 0: outputs in rad, > 0: optical path in m  */
 } qrfs_psd;
 
 /* Circular aperture of diameter D with central obstruction d (Eq. 7):
@@ -262,7 +288,10 @@ QRFS_API qrfs_status qrfs_sample_weights(qrfs_context* ctx, qrfs_sampler* s, int
  * 2 pi g(inf) (rad^2, of the piston when ap is given).
  * Errors: Kolmogorov model (g diverges at f = 0: QRFS_ERR_UNSUPPORTED);
  * r0, L0 <= 0; eps outside (0, 1); bad aperture; NULL N or df_out;
- * more than 2^31 steps. */
+ * more than 2^31 steps; QRFS_ERR_NOT_CONVERGED when the increments are
+ * still at or above eps g(inf) at the integration limit (200/D, or
+ * 2000/L0 without an aperture), i.e. eps is below what the rule can
+ * resolve there (*N, *df_out and *sigma2 are then left unchanged). */
 QRFS_API qrfs_status qrfs_choose_cartesian(const qrfs_psd* psd, const qrfs_aperture* ap,
                                            double df, double eps, int32_t* N, double* df_out,
                                            double* sigma2);
@@ -561,8 +590,17 @@ QRFS_API qrfs_status qrfs_batch_create(qrfs_context* ctx, int64_t n,
 #define QRFS_BATCH_SHAPES 5
 /* Times every candidate launch shape on this batch and keeps the fastest;
  * synchronises the stream.  best_ms (host, may be NULL) receives its time
- * in ms. */
-QRFS_API qrfs_status qrfs_batch_autotune(qrfs_batch* b, void* stream, double* best_ms);
+ * in ms.  cache_path (host string, may be NULL): a text file of earlier
+ * choices, one line "qrfs-autotune-1 <key> <shape> <ms>" per tuned batch,
+ * the key a 64-bit hash (hex) of the device's architecture name and compute
+ * unit count, the precision and every instance's K, P, R, R_block and
+ * aperture/tilt flags.  When the file holds the key, its (last) shape is
+ * selected without timing and its ms returned; otherwise the batch is timed
+ * and a line appended.  A missing file is an empty cache.
+ * Errors: NULL batch; the cache file cannot be appended to
+ * (QRFS_ERR_INVALID_ARG, after the tuned shape was selected); HIP errors. */
+QRFS_API qrfs_status qrfs_batch_autotune(qrfs_batch* b, void* stream, const char* cache_path,
+                                         double* best_ms);
 /* Selects launch shape `shape` (an implementation knob, for callers that
  * tune offline).  Errors: shape outside [0, QRFS_BATCH_SHAPES); the
  * two-phase shape when its tiles exceed the cap (QRFS_ERR_UNSUPPORTED);

@@ -44,7 +44,7 @@ def _load():
         "oracle_psd_constant": (_d, []),
         "oracle_psd": (_d, [_i32, _d, _d, _d, _d]),
         "oracle_aperture_filter": (_d, [_d, _d, _d]),
-        "oracle_weights": (None, [_i32, _d, _d, _d, _i32, _d, _d, _i64, _p, _p, _p, _p]),
+        "oracle_weights": (None, [_i32, _d, _d, _d, _i32, _d, _d, _d, _i64, _p, _p, _p, _p]),
         "oracle_philox4x32_10": (None, [_p, _p, _p]),
         "oracle_coefficients": (None, [_u64, _u64, _i64, _i32, _p]),
         "oracle_synthesize": (None, [_i64, _p, _p, _p, _i64, _p, _p, _i64, _i64, _u64, _u64,
@@ -65,7 +65,7 @@ def _load():
         "oracle_point_set_measures": (None, [_i64, _i64, _p, _p, _d, _d, _d, _d, _d, _p, _p,
                                              _p]),
         "oracle_set_sf_expectation": (None, [_i64, _p, _p, _p, _i64, _i64, _p, _p, _p]),
-        "oracle_choose_cartesian": (_i64, [_i32, _d, _d, _d, _i32, _d, _d, _d, _d, _p]),
+        "oracle_choose_cartesian": (_i64, [_i32, _d, _d, _d, _i32, _d, _d, _d, _d, _d, _p]),
         "oracle_temporal_experiment": (None, [_i64, _p, _p, _p, _p, _p, _p, _d, _i64, _i64,
                                               _i64, _u64, _u64, _i32, _p, _p]),
     }
@@ -207,12 +207,15 @@ def set_sf_expectation(fx, fy, w, n_sets, K, bx, by):
     return S
 
 
-def choose_cartesian(df, eps, r0=0.1, L0=25.0, D=None, d=0.0, c=None, model=PSD_VON_KARMAN):
-    """Stopping rule for N (Sec. 4.3): returns (N, sigma^2) with N df = 2 max f."""
+def choose_cartesian(df, eps, r0=0.1, L0=25.0, D=None, d=0.0, c=None, model=PSD_VON_KARMAN,
+                     wavelength=0.0):
+    """Stopping rule for N (Sec. 4.3): returns (N, sigma^2) with N df = 2 max f
+    (N = -1: not settled within the integration range)."""
     c = psd_constant() if c is None else c
     s2 = ctypes.c_double(0.0)
     N = _load().oracle_choose_cartesian(model, c, r0, L0, 0 if D is None else 1,
-                                        0.0 if D is None else D, d, df, eps, ctypes.byref(s2))
+                                        0.0 if D is None else D, d, df, eps, wavelength,
+                                        ctypes.byref(s2))
     return int(N), s2.value
 
 
@@ -233,13 +236,14 @@ def aperture_filter(f, D, d=0.0):
     return np.array([lib.oracle_aperture_filter(D, d, float(x)) for x in f])
 
 
-def weights(fx, fy, area, model=PSD_VON_KARMAN, c=None, r0=0.1, L0=25.0, D=None, d=0.0):
+def weights(fx, fy, area, model=PSD_VON_KARMAN, c=None, r0=0.1, L0=25.0, D=None, d=0.0,
+            wavelength=0.0):
     c = psd_constant() if c is None else c
     fx, fy, area = _f64(fx), _f64(fy), _f64(area)
     w = np.zeros(fx.size)
     has_ap = 0 if D is None else 1
-    _load().oracle_weights(model, c, r0, L0, has_ap, D or 0.0, d, fx.size, _ptr(fx), _ptr(fy),
-                           _ptr(area), _ptr(w))
+    _load().oracle_weights(model, c, r0, L0, has_ap, D or 0.0, d, wavelength, fx.size, _ptr(fx),
+                           _ptr(fy), _ptr(area), _ptr(w))
     return w
 
 

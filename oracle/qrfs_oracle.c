@@ -303,13 +303,16 @@ ORACLE_API double oracle_aperture_filter(double D, double d, double f) {
 /* w_k = sqrt(W(|f_k|) * area_k) [* F(|f_k|)], the amplitude factor of Eq. 3
  * (sqrt(delta_f_x delta_f_y W)).  has_ap = 0: phase; 1: piston filter. */
 ORACLE_API void oracle_weights(int32_t model, double c, double r0, double L0,
-                               int32_t has_ap, double D, double d, int64_t n,
-                               const double* fx, const double* fy, const double* area,
-                               double* w) {
+                               int32_t has_ap, double D, double d, double wavelength,
+                               int64_t n, const double* fx, const double* fy,
+                               const double* area, double* w) {
     for (int64_t i = 0; i < n; ++i) {
         double f = sqrt(fx[i] * fx[i] + fy[i] * fy[i]);
         double v = sqrt(oracle_psd(model, c, r0, L0, f) * area[i]);
         if (has_ap) v *= oracle_aperture_filter(D, d, f);
+        /* optical path instead of phase: OPD = (lambda / 2 pi) phase, the
+         * conversion of the structure function in Sec. 4.4 */
+        if (wavelength > 0.0) v *= wavelength / (2.0 * M_PI);
         w[i] = v;
     }
 }
@@ -558,7 +561,11 @@ ORACLE_API void oracle_tilt(int64_t K, const double* fx, const double* fy, const
  * g(inf) is the sum of the increments up to x_max = 200/D with an
  * aperture, 2000/L0 without (the integrand decays faster than f^-5 and as
  * f^-8/3: the tails left out are below 1e-7 and 3e-6 of g(inf)).
- * Returns N, or 0 for the Kolmogorov model (g diverges at f = 0). */
+ * Returns N, or 0 for the Kolmogorov model (g diverges at f = 0), or -1
+ * when even the last increment below x_max reaches eps g(inf) (the rule has
+ * not settled within the integration range).  With wavelength > 0 the
+ * variance is that of the optical path, (lambda / 2 pi)^2 times the phase
+ * variance (Sec. 4.4). */
 static double filtered_radial(int32_t model, double c, double r0, double L0, int32_t has_ap,
                               double D, double d, double f) {
     if (f <= 0.0) return 0.0;
@@ -569,7 +576,7 @@ static double filtered_radial(int32_t model, double c, double r0, double L0, int
 
 ORACLE_API int64_t oracle_choose_cartesian(int32_t model, double c, double r0, double L0,
                                            int32_t has_ap, double D, double d, double df,
-                                           double eps, double* sigma2) {
+                                           double eps, double wavelength, double* sigma2) {
     if (model != 1) return 0;
     double x_max = has_ap ? 200.0 / D : 2000.0 / L0;
     int64_t n_max = (int64_t)ceil(x_max / df);
@@ -595,7 +602,9 @@ ORACLE_API int64_t oracle_choose_cartesian(int32_t model, double c, double r0, d
             break;
         }
     free(inc);
-    if (sigma2) *sigma2 = 2.0 * M_PI * total;
+    if (nstar == n_max) return -1;
+    double s = wavelength > 0.0 ? wavelength / (2.0 * M_PI) : 1.0;
+    if (sigma2) *sigma2 = 2.0 * M_PI * total * s * s;
     return 2 * nstar;
 }
 

@@ -21,6 +21,7 @@ ERR_INVALID_ARG = -1
 ERR_OUT_OF_MEMORY = -2
 ERR_DEVICE = -3
 ERR_UNSUPPORTED = -4
+ERR_NOT_CONVERGED = -5
 
 PSD_KOLMOGOROV = 0
 PSD_VON_KARMAN = 1
@@ -50,7 +51,7 @@ class QrfsError(RuntimeError):
 
 class Psd(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("c", ctypes.c_double), ("r0", ctypes.c_double),
-                ("L0", ctypes.c_double)]
+                ("L0", ctypes.c_double), ("wavelength", ctypes.c_double)]
 
 
 class Aperture(ctypes.Structure):
@@ -76,10 +77,12 @@ class BatchInstance(ctypes.Structure):
                 ("uy", ctypes.c_double)]
 
 
-def psd(r0, L0=None, model=None, c=0.0):
+def psd(r0, L0=None, model=None, c=0.0, wavelength=0.0):
+    """Phase PSD; r0 at `wavelength`.  wavelength > 0 (m) makes every
+    PSD-weighted output optical path (m, m^2) instead of phase (rad, rad^2)."""
     if model is None:
         model = PSD_KOLMOGOROV if L0 is None else PSD_VON_KARMAN
-    return Psd(model, c, r0, 0.0 if L0 is None else L0)
+    return Psd(model, c, r0, 0.0 if L0 is None else L0, wavelength)
 
 
 def logpolar_sampler(fmin, fmax, index=0, seed_x=SEED_HALF, seed_y=SEED_HALF):
@@ -156,7 +159,7 @@ def load_library():
         "qrfs_error_string": (ctypes.c_char_p, [S]),
         "qrfs_last_error_detail": (ctypes.c_char_p, []),
         "qrfs_abi_version": (ctypes.c_int32, []),
-        "qrfs_context_create": (S, [ctypes.POINTER(_P), _I32]),
+        "qrfs_context_create": (S, [ctypes.POINTER(_P), _I32, ctypes.c_size_t]),
         "qrfs_context_destroy": (S, [_P]),
         "qrfs_context_set_tuning": (S, [_P, _I32, _I64]),
         "qrfs_choose_cartesian": (S, [ctypes.POINTER(Psd), ctypes.POINTER(Aperture), ctypes.c_double,
@@ -214,7 +217,7 @@ def load_library():
     sig.update({
         "qrfs_batch_create": (S, [_P, _I64, ctypes.POINTER(BatchInstance), _I32,
                                   ctypes.POINTER(_P)]),
-        "qrfs_batch_autotune": (S, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
+        "qrfs_batch_autotune": (S, [_P, _P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)]),
         "qrfs_batch_execute": (S, [_P, _I32, _P]),
         "qrfs_batch_set_shape": (S, [_P, _I32]),
         "qrfs_batch_info": (S, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32),
@@ -256,13 +259,13 @@ def _ptr(t):
 class Context:
     """Owns a libqrfs context (device workspace) on one HIP device."""
 
-    def __init__(self, device=0):
+    def __init__(self, device=0, workspace_cap=0):
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: libqrfs needs an MI355X")
         self.device = torch.device("cuda", device)
         h = _P()
-        _check(lib.qrfs_context_create(ctypes.byref(h), device))
+        _check(lib.qrfs_context_create(ctypes.byref(h), device, int(workspace_cap)))
         self._h = h
 
     @property
@@ -513,9 +516,12 @@ class Batch:
         _check(lib.qrfs_batch_create(ctx.handle, len(instances), arr, precision, ctypes.byref(h)))
         self._h = h
 
-    def autotune(self):
+    def autotune(self, cache_path=None):
+        """Times the launch shapes and keeps the fastest; with cache_path, a
+        batch of the same sizes tuned before reuses the stored choice."""
         ms = ctypes.c_double(0.0)
-        _check(load_library().qrfs_batch_autotune(self._h, _stream(), ctypes.byref(ms)))
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(load_library().qrfs_batch_autotune(self._h, _stream(), path, ctypes.byref(ms)))
         return ms.value
 
     def execute(self, use_graph=False):

@@ -23,6 +23,7 @@ struct qrfs_context {
     int device = 0;
     void* ws = nullptr;
     size_t ws_size = 0;
+    size_t ws_cap = 0;          // 0: unbounded
     int wide_path = 0;          // QRFS_TUNE_WIDE_PATH
     int64_t range_freqs = 2048;  // QRFS_TUNE_RANGE_FREQS
     size_t tile_cap = (size_t)2 << 30;  // QRFS_TUNE_TILE_BYTES
@@ -74,12 +75,16 @@ bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
 
 qrfs_status ensure_workspace(qrfs_context* ctx, size_t bytes) {
     if (bytes <= ctx->ws_size) return QRFS_OK;
+    if (ctx->ws_cap && bytes > ctx->ws_cap)
+        return fail(QRFS_ERR_OUT_OF_MEMORY, "workspace of %zu bytes exceeds the context cap of %zu",
+                    bytes, ctx->ws_cap);
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before workspace growth");
     if (ctx->ws) (void)hipFree(ctx->ws);
     ctx->ws = nullptr;
     ctx->ws_size = 0;
     size_t sz = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
+    if (ctx->ws_cap && sz > ctx->ws_cap) sz = bytes;
     e = hipMalloc(&ctx->ws, sz);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -100,6 +105,8 @@ qrfs_status check_psd(const qrfs_psd* psd) {
     if (psd->model == QRFS_PSD_VON_KARMAN && (!(psd->L0 > 0.0) || !std::isfinite(psd->L0)))
         return fail(QRFS_ERR_INVALID_ARG, "von Karman L0 must be > 0 (got %g)", psd->L0);
     if (!std::isfinite(psd->c)) return fail(QRFS_ERR_INVALID_ARG, "PSD constant is not finite");
+    if (!(psd->wavelength >= 0.0) || !std::isfinite(psd->wavelength))
+        return fail(QRFS_ERR_INVALID_ARG, "wavelength must be >= 0 (got %g)", psd->wavelength);
     return QRFS_OK;
 }
 
@@ -243,7 +250,8 @@ qrfs_status wide_sum(qrfs_context* ctx, int precision, int basis, qrfs::SumArgs 
     const int64_t rts_set = cdiv(a.R_block, 256);
     // coefficient tiles take at most ctx->tile_cap of workspace per piece
     // (one 256-row block of one set at least)
-    const size_t cap = ctx->tile_cap;
+    size_t cap = ctx->tile_cap;
+    if (ctx->ws_cap && ctx->ws_cap < cap + 512) cap = ctx->ws_cap > 512 ? ctx->ws_cap - 512 : 0;
     const size_t set_bytes = (size_t)rts_set * 8 * row32;
     int64_t sets_piece = 1, rows_piece = a.R_block;
     if (set_bytes <= cap) {
@@ -383,6 +391,7 @@ const char* qrfs_error_string(qrfs_status s) {
         case QRFS_ERR_OUT_OF_MEMORY: return "out of device memory";
         case QRFS_ERR_DEVICE: return "device (HIP runtime) error";
         case QRFS_ERR_UNSUPPORTED: return "unsupported";
+        case QRFS_ERR_NOT_CONVERGED: return "not converged";
         default: return "unknown status";
     }
 }
@@ -391,7 +400,7 @@ const char* qrfs_last_error_detail(void) { return g_detail.c_str(); }
 
 int32_t qrfs_abi_version(void) { return QRFS_ABI_VERSION; }
 
-qrfs_status qrfs_context_create(qrfs_context** out, int32_t device) {
+qrfs_status qrfs_context_create(qrfs_context** out, int32_t device, size_t workspace_cap_bytes) {
     if (!out) return fail(QRFS_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     int n = 0;
@@ -402,6 +411,7 @@ qrfs_status qrfs_context_create(qrfs_context** out, int32_t device) {
     qrfs_context* c = new (std::nothrow) qrfs_context();
     if (!c) return fail(QRFS_ERR_OUT_OF_MEMORY, "host allocation of the context");
     c->device = device;
+    c->ws_cap = workspace_cap_bytes;
     *out = c;
     return ok();
 }
@@ -476,7 +486,7 @@ qrfs_status qrfs_weights(qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aper
     if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
     DeviceGuard g(ctx->device);
     if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
-    double c = psd->c > 0.0 ? psd->c : qrfs::kPsdConstant;
+    const double c = qrfs::psd_constant(psd->c, psd->wavelength);
     hipError_t e = qrfs::launch_weights(psd->model, c, psd->r0, psd->L0, ap ? 1 : 0,
                                         ap ? ap->D : 0.0, ap ? ap->d : 0.0, n, fx, fy, area, w,
                                         (hipStream_t)stream);
@@ -507,7 +517,7 @@ qrfs_status qrfs_sample_weights(qrfs_context* ctx, qrfs_sampler* s, int64_t n_se
         if ((st = ensure_workspace(ctx, (size_t)(n_sets * K) * sizeof(double)))) return st;
         area = (double*)ctx->ws;
     }
-    const double c = psd->c > 0.0 ? psd->c : qrfs::kPsdConstant;
+    const double c = qrfs::psd_constant(psd->c, psd->wavelength);
     hipError_t e =
         sample_weights_any(s, s->index, n_sets, K, psd, c, ap, fx, fy, area, w, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "sampler / weights launch");
@@ -594,7 +604,7 @@ qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
     double* area = (double*)(fbase + 2 * arr);
     double* w = (double*)(fbase + 3 * arr);
     hipStream_t stream_ = (hipStream_t)stream;
-    const double c = psd->c > 0.0 ? psd->c : qrfs::kPsdConstant;
+    const double c = qrfs::psd_constant(psd->c, psd->wavelength);
 
     for (int64_t s0 = 0; s0 < n_sets; s0 += spb) {
         int64_t s1 = s0 + spb < n_sets ? s0 + spb : n_sets;
@@ -784,7 +794,7 @@ qrfs_status qrfs_temporal_piston_structure(qrfs_context* ctx, const qrfs_psd* ps
     double* w = (double*)(fbase + 3 * arr);
     void* pist = fbase + 4 * arr;
     hipStream_t stream_ = (hipStream_t)stream;
-    const double c = psd->c > 0.0 ? psd->c : qrfs::kPsdConstant;
+    const double c = qrfs::psd_constant(psd->c, psd->wavelength);
 
     hipError_t e = qrfs::launch_taylor_points(c1, c2, v, dt, M, px, py, stream_);
     if (e != hipSuccess) return hip_fail(e, "point launch");

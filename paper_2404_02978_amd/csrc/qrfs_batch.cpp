@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstring>
 #include <new>
 #include <string>
 #include <vector>
@@ -87,6 +88,9 @@ qrfs_status check_instance(const qrfs_batch_instance& in, int64_t i) {
         return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: unknown PSD model", (long long)i);
     if (!(p.r0 > 0.0) || (p.model == QRFS_PSD_VON_KARMAN && !(p.L0 > 0.0)))
         return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: r0 and L0 must be > 0", (long long)i);
+    if (!std::isfinite(p.c) || !(p.wavelength >= 0.0) || !std::isfinite(p.wavelength))
+        return api_fail(QRFS_ERR_INVALID_ARG, "instance %lld: PSD constant or wavelength invalid",
+                        (long long)i);
     const qrfs_sampler& s = in.sampler;
     const int sc = s.scheme;
     if (sc == QRFS_SAMPLER_R2_CARTESIAN || sc == QRFS_SAMPLER_RANDOM_CARTESIAN ||
@@ -189,9 +193,24 @@ qrfs_status ensure_wide(qrfs_batch* b) {
     return QRFS_OK;
 }
 
+// A captured graph holds the device addresses of the work list and of the
+// two-phase buffers as kernel arguments; it is dropped whenever those are
+// rebuilt, so the next graph execution captures the new ones.
+void drop_graph(qrfs_batch* b) {
+    if (b->exec) {
+        (void)hipDeviceSynchronize();  // a replay in flight still reads its arguments
+        (void)hipGraphExecDestroy(b->exec);
+    }
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_shape = -1;
+}
+
 // Work list for the current shape: every (instance, set, row tile, column
 // tile), sorted by decreasing cost (rows x columns x K), stable.
 qrfs_status build_items(qrfs_batch* b) {
+    drop_graph(b);
     qrfs::BatchShape sh = qrfs::batch_shape(b->precision, b->shape);
     if (sh.wide) {
         qrfs_status s = ensure_wide(b);
@@ -247,7 +266,7 @@ qrfs_status enqueue(qrfs_batch* b, hipStream_t st) {
                                            in.K, s.N, s.df, s.fmin, s.fmax, b->fx[i], b->fy[i],
                                            b->area[i], st);
         if (e != hipSuccess) return hfail(e, "sampler launch");
-        const double c = in.psd.c > 0.0 ? in.psd.c : qrfs::kPsdConstant;
+        const double c = qrfs::psd_constant(in.psd.c, in.psd.wavelength);
         e = qrfs::launch_weights(in.psd.model, c, in.psd.r0, in.psd.L0, 0, 0.0, 0.0,
                                  b->n_sets[i] * in.K, b->fx[i], b->fy[i], b->area[i], b->w[i], st);
         if (e != hipSuccess) return hfail(e, "weights launch");
@@ -270,12 +289,60 @@ qrfs_status enqueue(qrfs_batch* b, hipStream_t st) {
     return QRFS_OK;
 }
 
-void drop_graph(qrfs_batch* b) {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
-    b->graph_shape = -1;
+// Key of a batch in the autotune cache: FNV-1a (64-bit) over the device's
+// architecture name and compute-unit count, the precision and each
+// instance's sizes and basis flags -- what the launch shapes' timings
+// depend on.
+uint64_t tuning_key(const qrfs_batch* b) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const void* p, size_t n) {
+        const unsigned char* c = (const unsigned char*)p;
+        for (size_t i = 0; i < n; ++i) {
+            h ^= c[i];
+            h *= 1099511628211ull;
+        }
+    };
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess)
+        mix(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof(prop.gcnArchName)));
+    mix(&b->n_cu, sizeof(b->n_cu));
+    mix(&b->precision, sizeof(b->precision));
+    for (int i = 0; i < b->n; ++i) {
+        const qrfs_batch_instance& in = b->inst[i];
+        const int64_t v[6] = {in.K, in.P, in.R, in.R_block, in.apD ? 1 : 0,
+                              (in.ux != 0.0 || in.uy != 0.0) ? 1 : 0};
+        mix(v, sizeof(v));
+    }
+    return h;
+}
+
+// Last line of the cache file with this key; false when there is none (a
+// missing or unreadable file is an empty cache).
+bool cache_lookup(const char* path, uint64_t key, int* shape, double* ms) {
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    while (fgets(line, sizeof(line), f)) {
+        unsigned long long k = 0;
+        int sh = -1;
+        double t = 0.0;
+        if (sscanf(line, "qrfs-autotune-1 %llx %d %lf", &k, &sh, &t) == 3 && k == key) {
+            *shape = sh;
+            *ms = t;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+bool cache_append(const char* path, uint64_t key, int shape, double ms) {
+    FILE* f = fopen(path, "a");
+    if (!f) return false;
+    const bool okw = fprintf(f, "qrfs-autotune-1 %016llx %d %.6f\n", (unsigned long long)key,
+                             shape, ms) > 0;
+    return (fclose(f) == 0) && okw;
 }
 
 }  // namespace
@@ -422,11 +489,27 @@ qrfs_status qrfs_batch_execute(qrfs_batch* b, int32_t use_graph, void* stream) {
     return api_ok();
 }
 
-qrfs_status qrfs_batch_autotune(qrfs_batch* b, void* stream, double* best_ms) {
+qrfs_status qrfs_batch_autotune(qrfs_batch* b, void* stream, const char* cache_path,
+                                double* best_ms) {
     if (!b) return api_fail(QRFS_ERR_INVALID_ARG, "batch is NULL");
     Guard g(b->device);
     if (!g.okay) return api_fail(QRFS_ERR_DEVICE, "cannot select device %d", b->device);
     hipStream_t st = (hipStream_t)stream;
+    uint64_t key = 0;
+    if (cache_path) {
+        key = tuning_key(b);
+        int shape = -1;
+        double ms = 0.0;
+        if (cache_lookup(cache_path, key, &shape, &ms) &&
+            shape >= 0 && shape < qrfs::batch_shape_count(b->precision) &&
+            !(qrfs::batch_shape(b->precision, shape).wide && !b->tile_bytes)) {
+            b->shape = shape;
+            qrfs_status s = build_items(b);
+            if (s) return s;
+            if (best_ms) *best_ms = ms;
+            return api_ok();
+        }
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -461,6 +544,8 @@ qrfs_status qrfs_batch_autotune(qrfs_batch* b, void* stream, double* best_ms) {
     b->shape = best;
     if ((s = build_items(b))) return s;
     if (best_ms) *best_ms = best_t;
+    if (cache_path && !cache_append(cache_path, key, best, best_t))
+        return api_fail(QRFS_ERR_INVALID_ARG, "cannot append to the autotune cache %s", cache_path);
     return api_ok();
 }
 

@@ -10,6 +10,18 @@ namespace qrfs {
 // Gamma(11/6)^2 / (2 pi^(11/3)) (24/5 Gamma(6/5))^(5/6) (Eq. 7 prints 0.02289).
 constexpr double kPsdConstant = 0.022895587108555181;
 
+// The PSD constant the weight kernels use: c (or kPsdConstant for c <= 0),
+// times (lambda / 2 pi)^2 when outputs are optical path (wavelength > 0):
+// w = sqrt(W area) is then lambda / (2 pi) times the phase weight (Sec. 4.4).
+inline double psd_constant(double c, double wavelength) {
+    double k = c > 0.0 ? c : kPsdConstant;
+    if (wavelength > 0.0) {
+        const double s = wavelength / (2.0 * 3.141592653589793);
+        k *= s * s;
+    }
+    return k;
+}
+
 enum Basis : int {
     BASIS_PHASE = 0,   // (cos, sin)(2 pi f.x_p) w_k
     BASIS_PISTON = 1,  // (cos, sin)(2 pi f.c_p) w_k F(D_p, d_p, |f_k|)

@@ -57,7 +57,9 @@ extern "C" qrfs_status qrfs_choose_cartesian(const qrfs_psd* psd, const qrfs_ape
     if (ap && (!(ap->D > 0.0) || !(ap->d >= 0.0) || !(ap->d < ap->D)))
         return api_fail(QRFS_ERR_INVALID_ARG, "aperture needs 0 <= d < D");
     if (!(df > 0.0)) df = 0.25 / psd->L0;
-    const double c = psd->c > 0.0 ? psd->c : qrfs::kPsdConstant;
+    if (!(psd->wavelength >= 0.0) || !std::isfinite(psd->wavelength))
+        return api_fail(QRFS_ERR_INVALID_ARG, "wavelength must be >= 0");
+    const double c = qrfs::psd_constant(psd->c, psd->wavelength);
     // far enough that the increments left out hold < 1e-6 of the variance
     const double x_max = ap ? 200.0 / ap->D : 2000.0 / psd->L0;
     const double steps = std::ceil(x_max / df);
@@ -72,6 +74,10 @@ extern "C" qrfs_status qrfs_choose_cartesian(const qrfs_psd* psd, const qrfs_ape
             nstar = n;
             break;
         }
+    if (nstar == n_max)
+        return api_fail(QRFS_ERR_NOT_CONVERGED,
+                        "increments still >= eps g(inf) at the integration limit %g (eps %g)",
+                        x_max, eps);
     *N = (int32_t)(2 * nstar);
     *df_out = df;
     if (sigma2) *sigma2 = 2.0 * 3.141592653589793 * total;

@@ -36,10 +36,12 @@ def test_exports_every_declared_symbol(q):
 
 def test_abi_version_and_strings(q):
     lib = q.load_library()
-    assert lib.qrfs_abi_version() == 3
+    assert lib.qrfs_abi_version() == 4
     assert lib.qrfs_error_string(0) == b"success"
     assert lib.qrfs_error_string(-1) == b"invalid argument"
+    assert lib.qrfs_error_string(-2) == b"out of device memory"
     assert lib.qrfs_error_string(-4) == b"unsupported"
+    assert lib.qrfs_error_string(-5) == b"not converged"
 
 
 def _null():
@@ -151,3 +153,23 @@ def test_choose_cartesian_matches_oracle(q):
     with pytest.raises(q.QrfsError) as e:
         q.choose_cartesian(q.psd(0.1), None, 0.01, 1e-3)
     assert e.value.status == q.ERR_UNSUPPORTED
+
+
+def test_choose_cartesian_optical_path_and_not_converged(q):
+    """With a wavelength the variance is that of the optical path (Sec. 4.4),
+    as the oracle computes it; an eps below what the rule resolves within its
+    integration range is QRFS_ERR_NOT_CONVERGED (the oracle's -1)."""
+    import oracle
+    lam = 2.2e-6
+    N, df, s2 = q.choose_cartesian(q.psd(0.15, 22.0, wavelength=lam), q.Aperture(8.0, 1.1), 0.0,
+                                   1e-4)
+    rN, rs2 = oracle.choose_cartesian(df, 1e-4, r0=0.15, L0=22.0, D=8.0, d=1.1, wavelength=lam)
+    assert N == rN and abs(s2 / rs2 - 1) < 1e-6
+    assert rN == oracle.choose_cartesian(df, 1e-4, r0=0.15, L0=22.0, D=8.0, d=1.1)[0]
+    assert oracle.choose_cartesian(0.25 / 22, 1e-11, r0=0.1, L0=22.0)[0] == -1
+    with pytest.raises(q.QrfsError) as e:
+        q.choose_cartesian(q.psd(0.1, 22.0), None, 0.0, 1e-11)
+    assert e.value.status == q.ERR_NOT_CONVERGED
+    with pytest.raises(q.QrfsError) as e:
+        q.choose_cartesian(q.psd(0.1, 22.0, wavelength=-1.0), None, 0.0, 1e-3)
+    assert e.value.status == q.ERR_INVALID_ARG

@@ -115,6 +115,24 @@ def test_batch_graph_replays(q, ctx, shape):
     b.close()
 
 
+@pytest.mark.parametrize("shape", [4, 0])
+def test_batch_graph_after_rebuilt_work_list(q, ctx, shape):
+    """A graph captured before the work list is rebuilt (set_shape to the same
+    shape, then the autotuner) is not replayed with the freed list: the next
+    graph execution captures the current one and matches the oracle."""
+    inst, refs = instances(q, 2)
+    b = q.Batch(ctx, inst, precision=3)
+    b.set_shape(shape)
+    check(b.execute(use_graph=True), refs, TOL[3], "first graph")
+    b.set_shape(shape)
+    check(b.execute(use_graph=True), refs, TOL[3], "graph after set_shape")
+    b.autotune()
+    for o in b.outputs:
+        o.fill_(float("nan"))
+    check(b.execute(use_graph=True), refs, TOL[3], "graph after autotune")
+    b.close()
+
+
 def test_batch_autotune(q, ctx):
     inst, refs = instances(q, 1)
     b = q.Batch(ctx, inst, precision=3)

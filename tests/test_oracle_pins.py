@@ -438,3 +438,22 @@ def test_diff_piston_limits():
         A.sf_vk([3.0], 0.1, 25.0)[0], rel=1e-4)
     # piston variance = phase variance filtered: below the phase variance
     assert C0 < A.variance_vk(0.1, 25.0)
+
+
+def test_optical_path_weights_are_achromatic():
+    """Optical path = (lambda / 2 pi) phase (Sec. 4.4) and r0 = r0(lambda)
+    grows as lambda^(6/5) (Sec. 4.1): the phase variance then falls as
+    lambda^-2, so OPD weights do not depend on the wavelength; and their
+    squares sum to (lambda / 2 pi)^2 times the closed-form band variance."""
+    fx, fy, area = oracle.sample_logpolar(1, 4096, 1e-3, 1e2)
+    lam0, r00 = 0.5e-6, 0.1
+    ref = None
+    for lam in (0.5e-6, 1.65e-6, 2.2e-6, 10e-6):
+        r0 = r00 * (lam / lam0) ** 1.2
+        w = oracle.weights(fx, fy, area, r0=r0, L0=25.0, D=1.8, wavelength=lam)
+        if ref is None:
+            ref = w
+        assert np.max(np.abs(w - ref)) <= 1e-13 * np.max(np.abs(ref))
+        w = oracle.weights(fx, fy, area, r0=r0, L0=25.0, wavelength=lam)
+        band = A.variance_truncated(r0, 25.0, 1e-3, 1e2) * (lam / (2 * np.pi)) ** 2
+        assert np.sum(w * w) == pytest.approx(band, rel=2e-3)
