@@ -382,6 +382,28 @@ QRFS_API qrfs_status qrfs_diff_piston_structure_sets(qrfs_context* ctx, int64_t 
                                                      double* sf, double* sf_stderr,
                                                      void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as qrfs_diff_piston_structure_sets, with arguments, layouts and
+ * errors as there, computed without any allocation.  Its scratch (per-tile
+ * partial sums and split-K partials) is a static device array of 64 MiB
+ * that each GPU the library runs on holds until the process ends; its
+ * address on the context's device is looked up once, when the first
+ * context on that device is created.  To fit, the sums may take fewer
+ * frequency ranges (split-K) than qrfs_diff_piston_structure_sets would,
+ * so results agree to rounding (bit-equal when the plan is the same).
+ * Every call on one GPU shares that array: calls that overlap in time on
+ * one GPU (other streams, threads or contexts) race; nothing in it needs
+ * clearing between calls.  Extra error: a problem whose scratch exceeds
+ * 64 MiB even with one range (QRFS_ERR_INVALID_ARG).  With one range the
+ * scratch is 16 nB bytes per row tile of a set (tiles of at most 128 rows;
+ * one tile per set when R_block = 1), e.g. up to 131072 realisations of
+ * 32 baselines at R_block = 1; larger problems are split over calls. */
+QRFS_API qrfs_status qrfs_diff_piston_structure_sets_noalloc(
+    qrfs_context* ctx, int64_t K, const double* fx, const double* fy, const double* w,
+    int64_t nB, const double* bx, const double* by, int64_t R, int64_t R_block,
+    const qrfs_rng* rng, int32_t precision, double* sf, double* sf_stderr, void* stream);
+
 /* ----------------------------------------------- frozen-flow time series */
 /* Temporal structure function of the differential piston (the statistical
  * test of Sec. 4.4): pistons [R][2][M] hold, per realisation, the pistons of

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 
@@ -29,7 +30,19 @@ struct qrfs_context {
     size_t tile_cap = (size_t)2 << 30;  // QRFS_TUNE_TILE_BYTES
 };
 
+// Scratch of the allocation-free structure-function entry point: a static
+// device array (each GPU the library runs on holds its own copy until the
+// process ends), never allocated or freed by the library.  In host code
+// `scratch` names a host-side stand-in; kernels get the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
 
 thread_local std::string g_detail;
 
@@ -66,6 +79,30 @@ qrfs_status hip_fail(hipError_t e, const char* what) {
 }
 
 bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+
+// Looks up the device address of `scratch` on `device` (which must be
+// current) once per device.
+hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipSuccess;  // entry point then refuses
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+qrfs_status sf_sets_enqueue(const qrfs::SfPlan& plan, char* base, int64_t K, const double* fx,
+                            const double* fy, const double* w, int64_t nB, const double* bx,
+                            const double* by, int64_t R, int64_t R_block, const qrfs_rng* rng,
+                            int32_t precision, double* sf, double* sf_stderr, hipStream_t stream);
+
+void* scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 #define CHECK_PTR(p)                                                                 \
     do {                                                                             \
@@ -408,6 +445,12 @@ qrfs_status qrfs_context_create(qrfs_context** out, int32_t device, size_t works
     if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
     if (device < 0 || device >= n)
         return fail(QRFS_ERR_INVALID_ARG, "device %d out of range (%d devices)", device, n);
+    {
+        DeviceGuard g(device);
+        if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", device);
+        e = scratch_setup(device);
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the static scratch");
+    }
     qrfs_context* c = new (std::nothrow) qrfs_context();
     if (!c) return fail(QRFS_ERR_OUT_OF_MEMORY, "host allocation of the context");
     c->device = device;
@@ -859,13 +902,66 @@ qrfs_status qrfs_diff_piston_structure_sets(qrfs_context* ctx, int64_t K, const 
     if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
     DeviceGuard g(ctx->device);
     if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
-    const int64_t n_sets = cdiv(R, R_block);
     const qrfs::SfPlan plan = qrfs::sf_plan(precision, K, R, R_block, nB);
     const size_t partial_bytes = align256((size_t)(plan.n_partial_tiles * nB) * 2 * sizeof(double));
     const size_t phi_bytes = align256(plan.phi_floats * sizeof(float));
     if ((st = ensure_workspace(ctx, partial_bytes + phi_bytes))) return st;
-    double* partial = (double*)ctx->ws;
-    float* phi = (float*)((char*)ctx->ws + partial_bytes);
+    st = sf_sets_enqueue(plan, (char*)ctx->ws, K, fx, fy, w, nB, bx, by, R, R_block, rng,
+                         precision, sf, sf_stderr, (hipStream_t)stream);
+    return st ? st : ok();
+}
+
+qrfs_status qrfs_diff_piston_structure_sets_noalloc(qrfs_context* ctx, int64_t K,
+                                                    const double* fx, const double* fy,
+                                                    const double* w, int64_t nB,
+                                                    const double* bx, const double* by,
+                                                    int64_t R, int64_t R_block,
+                                                    const qrfs_rng* rng, int32_t precision,
+                                                    double* sf, double* sf_stderr,
+                                                    void* stream) {
+    qrfs_status st = check_sum_common(K, nB, R, R_block, rng, nullptr, precision);
+    if (st) return st;
+    CHECK_PTR(fx);
+    CHECK_PTR(fy);
+    CHECK_PTR(w);
+    CHECK_PTR(bx);
+    CHECK_PTR(by);
+    CHECK_PTR(sf);
+    if (sf_stderr && !aligned8(sf_stderr))
+        return fail(QRFS_ERR_INVALID_ARG, "sf_stderr is not 8-byte aligned");
+    if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    const qrfs::SfPlan plan = qrfs::sf_plan(precision, K, R, R_block, nB, kScratchBytes);
+    const size_t need = qrfs::sf_plan_bytes(plan, nB);
+    if (need > kScratchBytes)
+        return fail(QRFS_ERR_INVALID_ARG,
+                    "needs %zu bytes of scratch; the allocation-free entry point has %zu "
+                    "(fewer sets, realisations or baselines per call)",
+                    need, kScratchBytes);
+    void* base = scratch_ptr(ctx->device);
+    if (!base) return fail(QRFS_ERR_UNSUPPORTED, "no static scratch on device %d", ctx->device);
+    DeviceGuard g(ctx->device);
+    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
+    st = sf_sets_enqueue(plan, (char*)base, K, fx, fy, w, nB, bx, by, R, R_block, rng, precision,
+                         sf, sf_stderr, (hipStream_t)stream);
+    return st ? st : ok();
+}
+
+}  // extern "C"
+
+namespace {
+// The sums of qrfs_diff_piston_structure_sets over caller frequency sets,
+// with the plan's scratch at `base`: per-tile partials first, then the
+// split-K partial sums (every element the later kernels read is written
+// first, so the scratch needs no clearing).
+qrfs_status sf_sets_enqueue(const qrfs::SfPlan& plan, char* base, int64_t K, const double* fx,
+                            const double* fy, const double* w, int64_t nB, const double* bx,
+                            const double* by, int64_t R, int64_t R_block, const qrfs_rng* rng,
+                            int32_t precision, double* sf, double* sf_stderr, hipStream_t stream) {
+    qrfs_status st;
+    const int64_t n_sets = cdiv(R, R_block);
+    const size_t partial_bytes = align256((size_t)(plan.n_partial_tiles * nB) * 2 * sizeof(double));
+    double* partial = (double*)base;
+    float* phi = (float*)(base + partial_bytes);
     qrfs::SumArgs a{};
     a.K = K;
     a.fx = fx;
@@ -883,17 +979,14 @@ qrfs_status qrfs_diff_piston_structure_sets(qrfs_context* ctx, int64_t K, const 
     a.ksplit = plan.ksplit;
     a.kspan = plan.kspan;
     a.phi_part = phi;
-    if ((st = run_sum(precision, qrfs::BASIS_DIFF, qrfs::EPI_SFSUM, a, n_sets,
-                      (hipStream_t)stream)))
-        return st;
+    if ((st = run_sum(precision, qrfs::BASIS_DIFF, qrfs::EPI_SFSUM, a, n_sets, stream))) return st;
     if (plan.ksplit > 1) {
-        hipError_t e = qrfs::launch_sfsum_rows(phi, plan.ksplit, R, nB, partial, (hipStream_t)stream);
+        hipError_t e = qrfs::launch_sfsum_rows(phi, plan.ksplit, R, nB, partial, stream);
         if (e != hipSuccess) return hip_fail(e, "split-K square launch");
     }
     hipError_t e = qrfs::launch_reduce_sf(partial, plan.n_partial_tiles, nB, R, sf, sf_stderr,
-                                          (hipStream_t)stream);
+                                          stream);
     if (e != hipSuccess) return hip_fail(e, "reduction launch");
-    return ok();
+    return QRFS_OK;
 }
-
-}  // extern "C"
+}  // namespace

@@ -102,7 +102,12 @@ struct SfPlan {
     size_t phi_floats;
     int64_t n_partial_tiles;
 };
-SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P);
+// max_bytes > 0 bounds the scratch the plan needs (split-K partial sums
+// plus per-tile partials, each rounded up to 256 bytes) by taking fewer
+// frequency ranges; the plan may still exceed it with one range.
+SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P,
+               size_t max_bytes = 0);
+size_t sf_plan_bytes(const SfPlan& p, int64_t P);
 // Sets of one realisation and at most 64 baselines: the structure function
 // runs in k_sf_one (one block per realisation, one partial tile per set).
 bool sf_one_realisation(int64_t R_block, int64_t P);

@@ -1015,7 +1015,15 @@ int64_t sum_col_tiles(int precision, int basis, int64_t R_block, int64_t P) {
 
 bool sf_one_realisation(int64_t R_block, int64_t P) { return R_block == 1 && P <= 64; }
 
-SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P) {
+static size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t sf_plan_bytes(const SfPlan& p, int64_t P) {
+    return round256((size_t)(p.n_partial_tiles * P) * 2 * sizeof(double)) +
+           round256(p.phi_floats * sizeof(float));
+}
+
+SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P,
+               size_t max_bytes) {
     SfPlan p;
     const int64_t n_sets = cdiv(R, R_block);
     const int64_t rts = sum_row_tiles_per_set(precision, BASIS_DIFF, R_block, P);
@@ -1033,10 +1041,14 @@ SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P) 
         if (ks < 1) ks = 1;
         while (ks > 1 && (double)ks * R * P * 4.0 > (double)((size_t)1 << 30)) --ks;
     }
-    p.ksplit = (int)ks;
-    p.kspan = cdiv(cdiv(K, ks), KC) * KC;  // whole chunks, even frequency offsets
-    p.phi_floats = ks > 1 ? (size_t)ks * R * P : 0;
-    p.n_partial_tiles = ks > 1 ? cdiv(R, SF_ROWS) : n_sets * rts;
+    for (;;) {
+        p.ksplit = (int)ks;
+        p.kspan = cdiv(cdiv(K, ks), KC) * KC;  // whole chunks, even frequency offsets
+        p.phi_floats = ks > 1 ? (size_t)ks * R * P : 0;
+        p.n_partial_tiles = ks > 1 ? cdiv(R, SF_ROWS) : n_sets * rts;
+        if (ks == 1 || max_bytes == 0 || sf_plan_bytes(p, P) <= max_bytes) break;
+        --ks;
+    }
     return p;
 }
 
