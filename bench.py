@@ -30,17 +30,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "synthesized terms/s (R·K·P) and realisations/s at fixed error, plain vs chosen"
-PEAKS = {"fp32": 157.3, "split_bf16": 2500.0, "bf16x6": 2500.0, "fp64": 78.6}  # dense TFLOP/s
+PEAKS = {"fp32": 157.3, "split_bf16": 2500.0, "bf16x6": 2500.0, "fp16x3": 2500.0, "fp64": 78.6}  # dense TFLOP/s
 # vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane op per cycle
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # algorithmic vector ops of the generator per coefficient: Philox4x32-10
 # (10 rounds x (2 products + 2 three-input xors) per 4 words = 10), uniform
 # (2: one funnel shift and one subtraction), Box-Muller (4 per coefficient),
 # operand split (5.5 three-way, 3 two-way, two values per conversion)
-OPS_PER_COEF = {"bf16x6": 21.5, "split_bf16": 19.0}
+OPS_PER_COEF = {"bf16x6": 21.5, "split_bf16": 19.0, "fp16x3": 18.0}
 # per (frequency, column, row tile): FP64 product and range reduction (5),
 # difference basis sin, sin^2 (5), amplitude (2), split of 2 values
-OPS_PER_BASIS = {"bf16x6": 23.0, "split_bf16": 18.0}
+OPS_PER_BASIS = {"bf16x6": 23.0, "split_bf16": 18.0, "fp16x3": 16.0}
 # one realisation per set (k_sf_one): generator without the operand split,
 # plus the amplitude and the basis constants folded into each frequency's two
 # coefficients (2 per coefficient); per (frequency, baseline) the FP64
@@ -48,10 +48,10 @@ OPS_PER_BASIS = {"bf16x6": 23.0, "split_bf16": 18.0}
 # (2 sines, the half angle and a square) and the two FMAs of the contraction
 OPS_PER_COEF_F32 = 18.0
 OPS_PER_BASIS_ONE = 11.0
-PREC_IDS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "bf16x6": 3}
+PREC_IDS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "bf16x6": 3, "fp16x3": 4}
 # MFMA FLOPs executed per algorithmic flop (split-BF16 runs 3 products, BF16x6 six)
-MFMA_PASSES = {"fp32": 1, "split_bf16": 3, "bf16x6": 6, "fp64": 1}
-DTYPES = {"fp32": "f32", "split_bf16": "bf16x3", "bf16x6": "bf16x6", "fp64": "f64"}
+MFMA_PASSES = {"fp32": 1, "split_bf16": 3, "bf16x6": 6, "fp16x3": 3, "fp64": 1}
+DTYPES = {"fp32": "f32", "split_bf16": "bf16x3", "bf16x6": "bf16x6", "fp16x3": "fp16x3", "fp64": "f64"}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
 # a 1 GiB copy (x2.0 / x1.0), valid only for the kernel source they were taken with
 # sources the structure-function kernels are built from (hashed together)

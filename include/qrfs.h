@@ -237,11 +237,24 @@ typedef struct {
  *               hi.lo, mid.mid, lo.hi) on bf16 MFMA: FP32-class accuracy on
  *               the matrix cores, which run concurrently with the vector ALU
  *               that draws the coefficients (FP32 MFMA shares the vector
- *               datapath and does not); output float. */
+ *               datapath and does not); output float.
+ *   FP16X3      each operand split into fp16 hi (the truncation to 11
+ *               significant bits) + lo (the rounded remainder): 22
+ *               significant bits, three products (lo.hi, hi.lo, hi.hi) on
+ *               fp16 MFMA with FP32 accumulation; the basis amplitudes of
+ *               each block's frequency range are scaled by a power of two
+ *               into the fp16 range and the sums scaled back exactly.
+ *               FP32-class accuracy (per-product error <= 2^-19 relative, an
+ *               absolute floor of 2^-25 times the range's scale) with half
+ *               the operand-split work and half the products of BF16X6.
+ *               Fused kernel only: qrfs_synthesize_phase, qrfs_piston,
+ *               qrfs_tilt, qrfs_diff_piston and the structure functions;
+ *               batches refuse it (QRFS_ERR_UNSUPPORTED); output float. */
 #define QRFS_PREC_FP64 0
 #define QRFS_PREC_FP32 1
 #define QRFS_PREC_SPLIT_BF16 2
 #define QRFS_PREC_BF16X6 3
+#define QRFS_PREC_FP16X3 4
 
 /* ---------------------------------------------------------- entry points */
 

@@ -39,6 +39,7 @@ PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_SPLIT_BF16 = 2
 PREC_BF16X6 = 3
+PREC_FP16X3 = 4
 SEED_HALF = 1 << 63
 
 

@@ -192,7 +192,8 @@ qrfs_status check_sum_common(int64_t K, int64_t P, int64_t R, int64_t R_block,
     if (K > ((int64_t)1 << 33))
         return fail(QRFS_ERR_INVALID_ARG, "K too large for the 32-bit Philox block counter");
     if (precision != QRFS_PREC_FP64 && precision != QRFS_PREC_FP32 &&
-        precision != QRFS_PREC_SPLIT_BF16 && precision != QRFS_PREC_BF16X6)
+        precision != QRFS_PREC_SPLIT_BF16 && precision != QRFS_PREC_BF16X6 &&
+        precision != QRFS_PREC_FP16X3)
         return fail(QRFS_ERR_INVALID_ARG, "unknown precision %d", precision);
     if (!coef) {
         if (!rng) return fail(QRFS_ERR_INVALID_ARG, "rng is NULL and no coefficients were given");
@@ -266,7 +267,8 @@ qrfs_status run_sum(int precision, int basis, int epi, qrfs::SumArgs a, int64_t 
 // outputs wide enough to amortise the coefficient tiles, and enough
 // 256 x 256 tiles to fill the chip (or forced by the context).
 bool use_wide(const qrfs_context* ctx, int precision, int64_t P, int64_t R, int64_t R_block) {
-    if (precision == QRFS_PREC_FP64 || ctx->wide_path == 1) return false;
+    if (precision == QRFS_PREC_FP64 || precision == QRFS_PREC_FP16X3 || ctx->wide_path == 1)
+        return false;  // FP16X3 contracts in the fused kernel only
     if (P > ((int64_t)1 << 22)) return false;  // 256 rows of output within 32-bit tile offsets
     if (ctx->wide_path == 2) return true;
     const int64_t tiles = cdiv(R, R_block) * cdiv(R_block, 256) * cdiv(P, 256);
@@ -753,7 +755,8 @@ qrfs_status qrfs_temporal_sf(qrfs_context* ctx, int64_t R, int64_t M, int32_t pr
         return fail(QRFS_ERR_INVALID_ARG, "M must be in [1, %d] (got %lld)", qrfs::TEMPORAL_MAX_M,
                     (long long)M);
     if (precision != QRFS_PREC_FP64 && precision != QRFS_PREC_FP32 &&
-        precision != QRFS_PREC_SPLIT_BF16 && precision != QRFS_PREC_BF16X6)
+        precision != QRFS_PREC_SPLIT_BF16 && precision != QRFS_PREC_BF16X6 &&
+        precision != QRFS_PREC_FP16X3)
         return fail(QRFS_ERR_INVALID_ARG, "unknown precision %d", precision);
     if (!pistons) return fail(QRFS_ERR_INVALID_ARG, "pistons is NULL");
     if (((uintptr_t)pistons & (precision == QRFS_PREC_FP64 ? 7u : 3u)) != 0)

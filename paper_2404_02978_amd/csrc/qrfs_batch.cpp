@@ -357,6 +357,8 @@ qrfs_status qrfs_batch_create(qrfs_context* ctx, int64_t n, const qrfs_batch_ins
     if (!inst) return api_fail(QRFS_ERR_INVALID_ARG, "instances are NULL");
     if (precision == QRFS_PREC_FP64)
         return api_fail(QRFS_ERR_UNSUPPORTED, "batches run on the matrix cores (no FP64 path)");
+    if (precision == QRFS_PREC_FP16X3)
+        return api_fail(QRFS_ERR_UNSUPPORTED, "batches take FP32, split-BF16 or BF16x6");
     if (precision != QRFS_PREC_FP32 && precision != QRFS_PREC_SPLIT_BF16 &&
         precision != QRFS_PREC_BF16X6)
         return api_fail(QRFS_ERR_INVALID_ARG, "unknown precision %d", precision);

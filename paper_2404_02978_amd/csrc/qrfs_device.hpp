@@ -114,6 +114,25 @@ __device__ __forceinline__ void box_muller_f32(float u1, float u2, float& g0, fl
     g1 = rho * s;
 }
 
+// The same coefficients divided by sqrt(2 ln 2): rho / sqrt(2 ln 2) =
+// sqrt(-log2 u1) needs no product (the negation is a free input modifier);
+// kernels that multiply every coefficient by an amplitude fold the factor
+// kBoxMullerLog2 into it.
+constexpr double kBoxMullerLog2 = 1.1774100225154747;  // sqrt(2 ln 2)
+__device__ __forceinline__ void gauss4_f32_log2(uint64_t seed, uint64_t real, uint32_t t,
+                                                float g[4]) {
+    U32x4 x = coef_block(seed, real, t);
+    float s, c;
+    float rho = __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(word_uniform_f32(x.x)));
+    sincos2pi_unit_f32(word_uniform_f32(x.y), s, c);
+    g[0] = rho * c;
+    g[1] = rho * s;
+    rho = __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(word_uniform_f32(x.z)));
+    sincos2pi_unit_f32(word_uniform_f32(x.w), s, c);
+    g[2] = rho * c;
+    g[3] = rho * s;
+}
+
 // Four consecutive coefficients c[4t .. 4t+3] of one realisation
 // (Gaussian cos/sin mode), binary32.
 __device__ __forceinline__ void gauss4_f32(uint64_t seed, uint64_t real, uint32_t t, float g[4]) {

@@ -324,6 +324,8 @@ constexpr int STR_H = 2 * KC + 8;    // 16-bit values per basis column
 // CSRC: coefficient source, 0 = Gaussian cos/sin from Philox, 1 = Eq. 3
 // form from Philox, 2 = caller-supplied array (compile-time, so the integer
 // generator of the unused mode never reaches the instruction stream).
+// CSRC 3: the Gaussian coefficients of CSRC 0 divided by sqrt(2 ln 2) (the
+// caller folds the factor into its amplitudes).
 template <int CSRC>
 __device__ __forceinline__ void coef4_src(const SumArgs& a, int64_t row, bool rowok, uint32_t t,
                                           float g[4]) {
@@ -339,6 +341,7 @@ __device__ __forceinline__ void coef4_src(const SumArgs& a, int64_t row, bool ro
         // stored or summed, so their (finite) coefficients need no masking;
         // masking would split the Philox chains into separate basic blocks
         if constexpr (CSRC == 0) gauss4_f32(a.seed, a.counter + (uint64_t)row, t, g);
+        else if constexpr (CSRC == 3) gauss4_f32_log2(a.seed, a.counter + (uint64_t)row, t, g);
         else coef4_f32(a.seed, a.counter + (uint64_t)row, t, 1, g);
     }
 }
@@ -549,14 +552,29 @@ __global__ __launch_bounds__(256) __attribute__((
 template <int PREC, int NB>
 struct MfmaSmem {
     static constexpr int NT = 32 * NB;
-    static constexpr int NPL = PREC == 2 ? 2 : 3;  // bf16 planes per operand (split modes)
+    static constexpr int NPL = PREC == 3 ? 3 : 2;  // 16-bit planes per operand (split modes)
     static constexpr int NBF = PREC == 1 ? 2 * NT * STR_F32 : 4;
     static constexpr int NBH = PREC >= 2 ? 2 * NT * STR_H : 8;
     __attribute__((aligned(16))) float sBf[NBF];
     __attribute__((aligned(16))) __bf16 sBp[NPL][NBH];
-    double sred[4][NT][2];
+    double sred[8][NT][2];
     double spx[NT], spy[NT], sD[NT], sd[NT];
+    double smax[8];  // FP16x3: per-wave largest amplitude / coefficient
 };
+
+// Largest value over the block of a per-thread value (all threads call it;
+// it synchronises the block).
+template <int PREC, int NB>
+__device__ __forceinline__ double block_max(double v, MfmaSmem<PREC, NB>& sm) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sm.smax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = sm.smax[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, sm.smax[i]);
+    return m;
+}
 
 // One output tile: rows [row tile rt of set sl], columns [column tile ct],
 // frequency range ks.  Called once per block by k_sum_mfma and once per
@@ -568,6 +586,11 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
                                          MfmaSmem<PREC, NB>& sm) {
     constexpr int NT = 32 * NB;
     constexpr int NPL = MfmaSmem<PREC, NB>::NPL;
+    // split precisions draw the Gaussians without the Box-Muller constant
+    // and fold it into the basis amplitudes (one product per frequency and
+    // column instead of one per pair of coefficients)
+    constexpr int CS = (PREC >= 2 && CSRC == 0) ? 3 : CSRC;
+    constexpr double kAmp = CS == 3 ? kBoxMullerLog2 : 1.0;
     float* sBf = sm.sBf;
     auto& sBp = sm.sBp;
     auto& sred = sm.sred;
@@ -630,6 +653,32 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
             }
         }
 
+    // FP16x3: the basis amplitudes of this frequency range (and caller-given
+    // coefficients) are scaled by powers of two into the fp16 range; the sums
+    // are scaled back exactly before the epilogue
+    double wscale = 1.0, cscale = 1.0;
+    float unscale = 1.0f;
+    if constexpr (PREC == 4) {
+        double m = 0.0;
+        for (int64_t k = kb + threadIdx.x; k < ke; k += blockDim.x) {
+            double v = fabs(w[k]);
+            if (BASIS == BASIS_PISTON) v *= fabs(grad_factor(a.grad, a.gx, a.gy, fx[k], fy[k]));
+            m = fmax(m, v);
+        }
+        f16_scale(block_max(m, sm) * kAmp, wscale, unscale);
+        if constexpr (CSRC == 2) {
+            const int64_t twoK = 2 * a.K;
+            const int64_t r1 = row_begin + MT < row_end ? row_begin + MT : row_end;
+            double mc = 0.0;
+            for (int64_t r = row_begin; r < r1; ++r)
+                for (int64_t j = 2 * kb + threadIdx.x; j < 2 * ke; j += blockDim.x)
+                    mc = fmax(mc, fabs(a.coef[r * twoK + j]));
+            float uc;
+            f16_scale(block_max(mc, sm) * 0.25, cscale, uc);  // coefficients below 2^15
+            unscale *= uc;
+        }
+    }
+
     const int64_t nchunks = (ke - kb + KC - 1) / KC;
     // frequency data of the first chunk for this thread's kk
     double nfx = 0.0, nfy = 0.0, nw = 0.0;
@@ -658,7 +707,7 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
             BASIS == BASIS_PISTON ? cw * grad_factor(a.grad, a.gx, a.gy, cfx, cfy) : cw;
         const double sh = BASIS == BASIS_PISTON ? grad_shift(a.grad) : 0.0;
         for (int pp = pp0; pp < NT; pp += cstep) {
-            double amp = gw;
+            double amp = gw * (kAmp * wscale);
             if (BASIS == BASIS_PISTON) amp *= (double)aperture_filter_f32(sD[pp], sd[pp], fmag);
             float cb, sb;
             basis_pair<BASIS>(cfx * spx[pp] + cfy * spy[pp] + sh, amp, cb, sb);
@@ -669,7 +718,10 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
             } else {
                 const int o = buf * NT * STR_H + pp * STR_H + 2 * kk;  // even
                 uint32_t pcs[NPL];
-                split_bf16x2<NPL>(cb, sb, pcs);
+                if constexpr (PREC == 4)
+                    split_f16x2(cb, sb, pcs);
+                else
+                    split_bf16x2<NPL>(cb, sb, pcs);
 #pragma unroll
                 for (int i = 0; i < NPL; ++i) *(uint32_t*)&sBp[i][o] = pcs[i];
             }
@@ -702,6 +754,39 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
                             acc[mw][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(
                                 av[m][mw][q], bv[nb][q], acc[mw][nb], 0, 0, 0);
             }
+        } else if constexpr (PREC == 4) {
+            // FP16x3: as below with two fp16 planes and three products
+            __syncthreads();
+#pragma unroll
+            for (int sg = 0; sg < KC / 8; ++sg) {
+                const uint32_t t = (uint32_t)(k0 / 2) + 4u * sg + 2u * (uint32_t)lh;
+                f16x8 ap[MW][2];
+#pragma unroll
+                for (int mw = 0; mw < MW; ++mw) {
+                    float g[8];
+                    coef4_src<CS>(a, myrow[mw], rowok[mw], t, g);
+                    coef4_src<CS>(a, myrow[mw], rowok[mw], t + 1u, g + 4);
+                    if constexpr (CSRC == 2) {
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) g[q] = (float)((double)g[q] * cscale);
+                    }
+                    split8_f16(g, ap[mw]);
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int off = buf * NT * STR_H + (nb * 32 + lr) * STR_H + 16 * sg + 8 * lh;
+                    const f16x8 b0 = *(const f16x8*)&sBp[0][off];
+                    const f16x8 b1 = *(const f16x8*)&sBp[1][off];
+#pragma unroll
+                    for (int mw = 0; mw < MW; ++mw) {
+                        f32x16 c = acc[mw][nb];
+                        c = mfma_f16(ap[mw][1], b0, c);  // smallest products first
+                        c = mfma_f16(ap[mw][0], b1, c);
+                        c = mfma_f16(ap[mw][0], b0, c);
+                        acc[mw][nb] = c;
+                    }
+                }
+            }
         } else {
             // each group of 8 contraction values draws its coefficients right
             // before its MFMAs: the generator's vector work runs beside the
@@ -714,8 +799,8 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
 #pragma unroll
                 for (int mw = 0; mw < MW; ++mw) {
                     float g[8];
-                    coef4_src<CSRC>(a, myrow[mw], rowok[mw], t, g);
-                    coef4_src<CSRC>(a, myrow[mw], rowok[mw], t + 1u, g + 4);
+                    coef4_src<CS>(a, myrow[mw], rowok[mw], t, g);
+                    coef4_src<CS>(a, myrow[mw], rowok[mw], t + 1u, g + 4);
                     split8_bf16<NPL>(g, ap[mw]);
                 }
 #pragma unroll
@@ -752,6 +837,15 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
                     for (int i = 0; i < 16; ++i) acc[mw][nb][i] = 0.0f;
                 }
         }
+    }
+
+    if constexpr (PREC == 4) {
+#pragma unroll
+        for (int mw = 0; mw < MW; ++mw)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) mst[mw][nb][i] *= unscale;
     }
 
     if (EPI == EPI_STORE) {
@@ -823,16 +917,23 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
 // The one-tile structure-function kernels (MW = NB = 1, EPI_SFSUM) are bound by
 // vector issue: asking for five waves per SIMD instead of the four their
 // registers give (a handful of spills outside the frequency loop, 30 KB of
-// LDS per block) hides more of the transcendental and MFMA latency.  BF16x6
+// LDS per block) hides more of the transcendental and MFMA latency; FP16x3
+// fits six (80 registers, its one spill outside the loop).  BF16x6
 // with Eq. 3 or caller-given coefficients keeps the default: at five waves
 // it reloads spilled registers inside the frequency loop.
 template <int PREC, int EPI, int MW, int NB, int CSRC>
 constexpr int sum_mfma_min_waves() {
-    return (EPI == EPI_SFSUM && MW * NB == 1 && (PREC < 3 || CSRC == 0)) ? 5 : 1;
+    return (EPI == EPI_SFSUM && MW * NB == 1 && (PREC < 3 || CSRC == 0)) ? (PREC == 4 ? 6 : 5) : 1;
+}
+
+// Blocks of the difference basis may hold 8 waves (256 rows), the others 4.
+template <int BASIS>
+constexpr int sum_mfma_max_threads() {
+    return BASIS == BASIS_DIFF ? 512 : 256;
 }
 
 template <int PREC, int BASIS, int EPI, int MW, int NB, int CSRC>
-__global__ __launch_bounds__(256) __attribute__((
+__global__ __launch_bounds__(sum_mfma_max_threads<BASIS>()) __attribute__((
     amdgpu_waves_per_eu(sum_mfma_min_waves<PREC, EPI, MW, NB, CSRC>(), 8))) void
 k_sum_mfma(SumArgs a, int64_t row_tiles, int64_t col_tiles) {
     __shared__ MfmaSmem<PREC, NB> sm;
@@ -998,6 +1099,9 @@ static MfmaShape mfma_shape(int precision, int basis, int64_t R_block, int64_t P
     }
     int64_t wv = cdiv(R_block, 32 * s.MW);
     s.WV = (int)(wv > 4 ? 4 : wv);
+    // differential pistons of at most 32 baselines: one block covers 256
+    // rows, so each set's difference basis is built once per 256 rows
+    if (precision >= 2 && basis == BASIS_DIFF && P <= 32 && wv >= 8) s.WV = 8;
     return s;
 }
 
@@ -1160,6 +1264,7 @@ static hipError_t launch_be(int precision, const SumArgs& a, hipStream_t st) {
         if (a.R_block <= 8) return launch_f32n<BASIS>(a, st);
     if (precision == 1) return launch_mfma<1, BASIS, EPI>(a, st);
     if (precision == 2) return launch_mfma<2, BASIS, EPI>(a, st);
+    if (precision == 4) return launch_mfma<4, BASIS, EPI>(a, st);
     return launch_mfma<3, BASIS, EPI>(a, st);
 }
 

@@ -54,6 +54,60 @@ __device__ __forceinline__ void split8_bf16(const float (&v)[8], bf16x8 (&o)[NPL
     for (int i = 0; i < NPL; ++i) o[i] = __builtin_bit_cast(bf16x8, w[i]);
 }
 
+// FP16x3 operands: x = hi + lo in fp16.  hi is x rounded to nearest fp16,
+// the remainder x - hi is exact in binary32 (one v_fma_mix_f32 that takes
+// hi as an fp16 operand: no conversion back), and lo is its rounding:
+// |x - hi - lo| <= 2^-22 |x| in the normal fp16 range and below 2^-25
+// absolute where hi or lo is an fp16 subnormal.  The caller keeps
+// |x| < 2^15.  Two values at once: hi and lo each as one packed word,
+// x0 in the low half (the element order of the MFMA operands).
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f32x16 mfma_f16(f16x8 a, f16x8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void split_f16x2(float x0, float x1, uint32_t part[2]) {
+    const f32x2 x = {x0, x1};
+    const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, f16x2));
+    float r0, r1;
+    // r = x - hi with hi read as fp16 from its half of the packed word
+    asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r0) : "v"(h), "v"(x0));
+    asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+        : "=v"(r1)
+        : "v"(h), "v"(x1));
+    const f32x2 r = {r0, r1};
+    part[0] = h;
+    part[1] = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, f16x2));
+}
+
+__device__ __forceinline__ void split8_f16(const float (&v)[8], f16x8 (&o)[2]) {
+    uint32_t w[2][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t part[2];
+        split_f16x2(v[2 * j], v[2 * j + 1], part);
+        w[0][j] = part[0];
+        w[1][j] = part[1];
+    }
+    o[0] = __builtin_bit_cast(f16x8, w[0]);
+    o[1] = __builtin_bit_cast(f16x8, w[1]);
+}
+
+// Power-of-two scale 2^s (and 2^-s) that brings a largest magnitude m into
+// [2^13, 2^14), so FP16x3 basis values (at most 2 m) stay below the fp16
+// maximum; s is clamped to [-100, 100] (1 for m = 0).
+__device__ __forceinline__ void f16_scale(double m, double& scale, float& unscale) {
+    int s = 0;
+    if (m > 0.0) {
+        s = 13 - ilogb(m);
+        s = s < -100 ? -100 : (s > 100 ? 100 : s);
+    }
+    scale = ldexp(1.0, s);
+    unscale = ldexpf(1.0f, -s);
+}
+
 template <int BASIS>
 __device__ __forceinline__ void basis_pair(double t, double amp, float& cb, float& sb) {
     float r = (float)frac_centered(t);

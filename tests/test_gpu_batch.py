@@ -85,6 +85,13 @@ def test_batch_every_shape(q, ctx, precision, shape):
     b.close()
 
 
+def test_batch_refuses_fp16x3(q, ctx):
+    inst, _ = instances(q, 1)
+    with pytest.raises(q.QrfsError) as e:
+        q.Batch(ctx, inst, precision=q.PREC_FP16X3)
+    assert e.value.status == q.ERR_UNSUPPORTED
+
+
 def test_batch_two_phase_is_default(q, ctx):
     inst, _ = instances(q, 1)
     b = q.Batch(ctx, inst, precision=2)

@@ -18,7 +18,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-11, 1: 1e-5, 2: 1e-5, 3: 1e-5}
+TOL = {0: 1e-11, 1: 1e-5, 2: 1e-5, 3: 1e-5, 4: 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -59,7 +59,7 @@ def _freqs(ctx, q, n_sets, K, index):
     return fx, fy, w
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2, 3])
+@pytest.mark.parametrize("precision", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("R_block", [2, 3, 5, 8])
 @pytest.mark.parametrize("P", [37, 130, 300])
 def test_narrow_phase(q, ctx, precision, R_block, P):
@@ -77,7 +77,7 @@ def test_narrow_phase(q, ctx, precision, R_block, P):
     report(f"narrow phase p{precision} Rb{R_block} P{P}", host(out), ref, TOL[precision])
 
 
-@pytest.mark.parametrize("precision", [0, 1, 3])
+@pytest.mark.parametrize("precision", [0, 1, 3, 4])
 @pytest.mark.parametrize("R_block", [1, 4, 6])
 def test_narrow_piston_and_tilt(q, ctx, precision, R_block):
     K, R = 150, 13

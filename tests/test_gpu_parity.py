@@ -19,8 +19,8 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-11, 1: 1e-5, 2: 1e-3, 3: 1e-5}
-PRECS = [0, 1, 2, 3]
+TOL = {0: 1e-11, 1: 1e-5, 2: 1e-3, 3: 1e-5, 4: 1e-5}
+PRECS = [0, 1, 2, 3, 4]
 
 
 @pytest.fixture(scope="module")
@@ -95,7 +95,7 @@ def test_sampler_disc(q, ctx):
     assert np.max(np.abs(host(area) / ra - 1)) < 1e-15
 
 
-@pytest.mark.parametrize("precision", [0, 3])
+@pytest.mark.parametrize("precision", [0, 3, 4])
 def test_structure_function_disc_sampler(q, ctx, precision):
     cfg = workloads.diffpiston()
     K, R, R_block, fmax = 600, 300, 100, 0.5
@@ -198,7 +198,7 @@ def test_synthesize_given_coefficients(q, ctx, precision):
     report(f"given coef p{precision}", host(out), ref, TOL[precision])
 
 
-@pytest.mark.parametrize("precision", [0, 1, 3])
+@pytest.mark.parametrize("precision", [0, 1, 3, 4])
 def test_synthesize_eq3_mode(q, ctx, precision):
     K, P, R = 123, 37, 70
     fx, fy, w = _freqs(ctx, q, 1, K)
@@ -272,7 +272,7 @@ def test_diff_piston_structure_parity(q, ctx, precision, R, R_block):
     fx, fy, area = oracle.sample_logpolar(n_sets, K, cfg["fmin"], cfg["fmax"], index=1234)
     w = oracle.weights(fx, fy, area, r0=0.1, L0=25.0, D=cfg["D"])
     rsf, rse = oracle.diff_piston_sf(fx, fy, w, cfg["bx"], cfg["by"], R, R_block, K=K, seed=9)
-    tol = {0: 1e-10, 1: 2e-5, 2: 2e-3, 3: 2e-5}[precision]
+    tol = {0: 1e-10, 1: 2e-5, 2: 2e-3, 3: 2e-5, 4: 2e-5}[precision]
     g, gs = host(sf), host(se)
     print(f"sf p{precision} R{R} Rb{R_block}: max rel {np.max(np.abs(g / rsf - 1)):.3e}")
     assert np.max(np.abs(g / rsf - 1)) < tol
@@ -338,15 +338,18 @@ def test_diff_piston_structure_full_size(q, ctx, R_block):
     assert np.all(np.abs(z) < 4.5)
 
 
-def test_diff_piston_structure_sets_full_size_bf16x6(q, ctx):
+@pytest.mark.parametrize("precision", [3, 4])
+def test_diff_piston_structure_sets_full_size(q, ctx, precision):
     """The benchmark's own launch sequence at full size: 1e5 realisations,
-    K = 16384, 32 baselines, R_block = 256, BF16x6, the frequency sets and
-    weights drawn in one pass and the sums taken from those sets.  (a) The
-    fused structure-function sums equal the mean squares of the stored
-    differential pistons of the same sets and coefficients; (b) sampled
-    realisations of those pistons equal the oracle's within the BF16x6
-    tolerance; (c) the estimate agrees with the analytic curve within its
-    statistical error."""
+    K = 16384, 32 baselines, R_block = 256, BF16x6 and FP16x3, the frequency
+    sets and weights drawn in one pass and the sums taken from those sets.
+    (a) The fused structure-function sums equal the mean squares of the
+    stored differential pistons of the same sets and coefficients; (b) 16
+    sampled realisations of those pistons equal the oracle's within the
+    FP32-class tolerance; (c) the structure function of two-set subsets (512
+    realisations at the start, the middle and the end, the same sets and
+    coefficient counters) equals the oracle's baseline by baseline; (d) the
+    estimate agrees with the analytic curve within its statistical error."""
     from oracle import analytic as A
     cfg = workloads.diffpiston()
     K, R, R_block = cfg["K"], cfg["R"], 256
@@ -359,21 +362,33 @@ def test_diff_piston_structure_sets_full_size_bf16x6(q, ctx):
     assert s.index == n_sets * K
     rng = q.Rng(0, 0, q.COEF_GAUSS_CS)
     sf, se = ctx.diff_piston_structure_sets(K, fx, fy, w, bx, by, R, R_block, rng=rng,
-                                            precision=q.PREC_BF16X6)
-    dp = ctx.diff_piston(K, fx, fy, w, bx, by, R, R_block, rng=rng, precision=q.PREC_BF16X6)
+                                            precision=precision)
+    dp = ctx.diff_piston(K, fx, fy, w, bx, by, R, R_block, rng=rng, precision=precision)
     dph = host(dp)
     mean_sq = np.mean(dph * dph, axis=0)
     assert np.max(np.abs(host(sf) / mean_sq - 1)) < 1e-6
     px = np.concatenate([[0.0], cfg["bx"]])
     py = np.concatenate([[0.0], cfg["by"]])
-    for r in (0, 255, 256, 77777, R - 1):
+    rows = [0, 255, 256, R - 1] + list(np.random.default_rng(precision).integers(0, R, 12))
+    for r in rows:
         sl = slice((r // R_block) * K, (r // R_block + 1) * K)
         pist = oracle.synthesize(host(fx[sl]), host(fy[sl]), host(w[sl]), px, py, 1, 1, K=K,
-                                 seed=0, counter=r)
+                                 seed=0, counter=int(r))
         ref = pist[0, 1:] - pist[0, 0]
         e = np.max(np.abs(dph[r] - ref)) / math.sqrt(np.mean(ref * ref))
         print(f"row {r}: eps_max {e:.3e}")
-        assert e < TOL[q.PREC_BF16X6]
+        assert e < TOL[precision]
+    for s0 in (0, n_sets // 2, n_sets - 3):
+        sl = slice(s0 * K, (s0 + 2) * K)
+        sub, _ = ctx.diff_piston_structure_sets(K, fx[sl], fy[sl], w[sl], bx, by, 2 * R_block,
+                                                R_block, rng=q.Rng(0, s0 * R_block, 0),
+                                                precision=precision)
+        ref, _ = oracle.diff_piston_sf(host(fx[sl]), host(fy[sl]), host(w[sl]), cfg["bx"],
+                                       cfg["by"], 2 * R_block, R_block, K=K, seed=0,
+                                       counter=s0 * R_block)
+        e = np.max(np.abs(host(sub) / ref - 1))
+        print(f"sets {s0}, {s0 + 1}: structure function max rel {e:.3e}")
+        assert e < 2e-5
     an = A.sf_band(cfg["bx"], cfg["r0"], 25.0, cfg["fmin"], cfg["fmax"], D=cfg["D"])
     z = (host(sf) - an) / host(se)
     print("z", np.round(z, 2))

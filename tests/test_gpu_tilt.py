@@ -17,7 +17,7 @@ from oracle import analytic as A
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-11, 1: 1e-5, 2: 1e-3, 3: 1e-5}
+TOL = {0: 1e-11, 1: 1e-5, 2: 1e-3, 3: 1e-5, 4: 1e-5}
 DIRS = [(1.0, 0.0), (0.0, 1.0), (0.6, -0.8)]
 
 
@@ -68,7 +68,7 @@ def _oracle_dir(u, fx, fy, w, cx, cy, D, d, R, R_block, K, seed, counter):
     return out
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2, 3])
+@pytest.mark.parametrize("precision", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("u", DIRS)
 @pytest.mark.parametrize("R,R_block", [(200, 64), (37, 1)])
 def test_tilt_parity_fused(q, ctx, precision, u, R, R_block):
