@@ -5,7 +5,7 @@ baselines log-spaced over 1-130 m, von Karman r0 = 0.1 m with L0 in
 {10, 25, 100} m, log-polar R2 frequencies over [1e-3, 1e2] cycles/m,
 K = 16384 frequencies per set, R = 100000 realisations per L0, R_block
 realisations per frequency set (default 256).  The contraction runs in
-BF16x6 by default (operands split three ways into bf16, six products on the
+FP16x3 by default (operands split into fp16 hi + lo, three products on the
 matrix cores, FP32-class accuracy: it meets the FP32 parity tolerance); the
 same workload with the FP32 MFMA contraction is timed as a reference.
 
@@ -15,7 +15,7 @@ with the structure-function epilogue and its reduction.  Inputs are
 resident in HBM; nothing is copied to or from the host inside the timed
 region.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--precision bf16x6]
+  python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--precision fp16x3]
   python bench.py --mode copy      (HBM counter calibration)
 """
 import argparse
@@ -33,21 +33,15 @@ METRIC = "synthesized terms/s (R·K·P) and realisations/s at fixed error, plain
 PEAKS = {"fp32": 157.3, "split_bf16": 2500.0, "bf16x6": 2500.0, "fp16x3": 2500.0, "fp64": 78.6}  # dense TFLOP/s
 # vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane op per cycle
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# algorithmic vector ops of the generator per coefficient: Philox4x32-10
-# (10 rounds x (2 products + 2 three-input xors) per 4 words = 10), uniform
-# (2: one funnel shift and one subtraction), Box-Muller (4 per coefficient),
-# operand split (5.5 three-way, 3 two-way, two values per conversion)
-OPS_PER_COEF = {"bf16x6": 21.5, "split_bf16": 19.0, "fp16x3": 18.0}
-# per (frequency, column, row tile): FP64 product and range reduction (5),
-# difference basis sin, sin^2 (5), amplitude (2), split of 2 values
-OPS_PER_BASIS = {"bf16x6": 23.0, "split_bf16": 18.0, "fp16x3": 16.0}
-# one realisation per set (k_sf_one): generator without the operand split,
-# plus the amplitude and the basis constants folded into each frequency's two
-# coefficients (2 per coefficient); per (frequency, baseline) the FP64
-# argument (2) and its reduction (2), a conversion, the difference basis
-# (2 sines, the half angle and a square) and the two FMAs of the contraction
-OPS_PER_COEF_F32 = 18.0
-OPS_PER_BASIS_ONE = 11.0
+FP32_VECTOR_PEAK = 157.3  # TFLOP/s, MI355X fp32 vector
+# the method's vector work: per coefficient Philox4x32-10 (10 rounds x
+# (2 products + 2 three-input xors) per 4 words = 10), the uniform (2: one
+# funnel shift and one subtraction) and Box-Muller (log, sqrt, sin, cos and
+# 2 products per pair: 4 per coefficient); per (frequency, baseline, set)
+# the FP64 product and range reduction (5), the difference basis sin,
+# sin^2 (5) and the amplitude (2)
+METHOD_OPS_PER_COEF = 16.0
+METHOD_OPS_PER_BASIS = 12.0
 PREC_IDS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "bf16x6": 3, "fp16x3": 4}
 # MFMA FLOPs executed per algorithmic flop (split-BF16 runs 3 products, BF16x6 six)
 MFMA_PASSES = {"fp32": 1, "split_bf16": 3, "bf16x6": 6, "fp16x3": 3, "fp64": 1}
@@ -65,7 +59,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=list(PREC_IDS), default="bf16x6")
+    ap.add_argument("--precision", choices=list(PREC_IDS), default="fp16x3")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: only a 1 GiB device-to-device copy, the reference for the "
                          "HBM byte counters")
@@ -75,7 +69,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle sample (0 disables it)")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the plain-vs-chosen comparison (learned proposal)")
+                    help="skip the realisations/s-at-fixed-error comparison (plain vs learned)")
     ap.add_argument("--workload", choices=["diffpiston", "phase", "large_screen", "batched",
                                            "temporal", "sampler_ablation"],
                     default="diffpiston",
@@ -97,17 +91,47 @@ def _time_call(fn, reps=3):
     return ts[len(ts) // 2]
 
 
-def plain_vs_chosen(q, ctx, cfg, L0=25.0, R=100000, R_block=256):
-    """The differential-piston structure function at L0 with the plain
-    method (uniform-in-log R2, K = 65536, FP64 arithmetic) and with the
-    chosen configuration (learned proposal, K = 4096, FP32-class BF16x6 and
-    split-BF16), both at R realisations: error against the band-limited
-    analytic curve (RMS over the 32 baselines) and realisations/s of the
-    end-to-end call (sampling, weights, sums).  The proposal is trained on
-    the plain method's contributions first (not timed)."""
+def train_proposal(q, ctx, cfg, L0, n_ctx=1024, m=2048, steps=2000):
+    """The learned proposal of the chosen configuration: trained on
+    n_ctx * m = 2.1e6 per-frequency variance contributions the plain method
+    generates (the contexts cover D, L0 and the baselines), then tabulated
+    for the benchmark's aperture, outer scale and 32 baselines."""
     import numpy as np
     import torch
     import workloads
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    ctxs = torch.as_tensor(workloads.proposal_contexts(n_ctx, seed=0), device=dev)
+    prop = q.Proposal(ctx, cfg["fmin"], cfg["fmax"], workloads.mlp_init(0).astype(np.float32))
+    plain_rows = q.logpolar_sampler(cfg["fmin"], cfg["fmax"], index=1 << 40)
+    ell, theta, h = prop.rows(plain_rows, ctxs, m, cfg["r0"])
+    loss = prop.train(ctxs, ell, theta, h, steps=steps, ctx_per_step=16, lr=2e-3, seed=1)
+    prop.tabulate(cfg["D"], L0, cfg["bx"], np.zeros(cfg["bx"].size))
+    torch.cuda.synchronize()
+    loss = loss.cpu().numpy()
+    info = {"rows": n_ctx * m, "contexts": n_ctx, "steps": steps,
+            "train_s": time.perf_counter() - t0,
+            "loss_first_last": [float(np.mean(loss[:20])), float(np.mean(loss[-20:]))]}
+    return prop, info
+
+
+def fixed_error(q, ctx, cfg, L0=25.0, R=100000, targets=(0.01, 0.002)):
+    """Realisations/s at a fixed error, plain vs chosen (the metric's second
+    half).  The error that K controls is the sampling error of the frequency
+    sets: given the sets, the coefficients make the estimate's expectation
+    the mean over the sets used of S_s(B) = sum_k w_k^2 2 (1 - cos 2 pi f_k.B)
+    (qrfs_set_sf_expectation), so E_S(K) = RMS over the 32 baselines of
+    that mean against the band-limited analytic curve is the noise-free
+    error.  For the plain sampler (log-polar R2) and the learned proposal,
+    and for R_block = 256 (391 sets of the continuing sequence) and
+    R_block = R (one static set, the case Sec. 2.3 warns about), the
+    smallest K on a grid 2^8 .. 2^18 with E_S(K) <= target is found; the
+    end-to-end structure function (sampling, weights, sums of R = 1e5
+    realisations) is then timed at that K in FP64 and in FP16x3.  The total
+    error of each timed run against the curve (noise included; the noise
+    floor is sqrt(2/R) = 0.45 % per baseline) is reported beside it."""
+    import numpy as np
+    import torch
     from oracle import analytic
     dev = torch.device("cuda", 0)
     bx = torch.as_tensor(cfg["bx"], dtype=torch.float64, device=dev)
@@ -115,46 +139,58 @@ def plain_vs_chosen(q, ctx, cfg, L0=25.0, R=100000, R_block=256):
     ap = q.Aperture(cfg["D"], 0.0)
     psd = q.psd(cfg["r0"], L0)
     an = analytic.sf_band(cfg["bx"], cfg["r0"], L0, cfg["fmin"], cfg["fmax"], D=cfg["D"])
+    prop, train = train_proposal(q, ctx, cfg, L0)
+    samplers = {"plain": lambda: q.logpolar_sampler(cfg["fmin"], cfg["fmax"]),
+                "learned": lambda: q.learned_sampler(prop)}
+    grid = [1 << e for e in range(8, 19)]
+    out = {"L0": L0, "R": R, "training": train, "K_grid": grid, "targets": list(targets),
+           "runs": {}}
 
-    t0 = time.perf_counter()
-    ctxs = torch.as_tensor(workloads.proposal_contexts(128, seed=0), device=dev)
-    prop = q.Proposal(ctx, cfg["fmin"], cfg["fmax"], workloads.mlp_init(0).astype(np.float32))
-    plain_rows = q.logpolar_sampler(cfg["fmin"], cfg["fmax"], index=1 << 40)
-    ell, theta, h = prop.rows(plain_rows, ctxs, 2048, cfg["r0"])
-    loss = prop.train(ctxs, ell, theta, h, steps=600, ctx_per_step=16, lr=2e-3, seed=1)
-    prop.tabulate(cfg["D"], L0, cfg["bx"], np.zeros(cfg["bx"].size))
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    loss = loss.cpu().numpy()
+    def e_s(name, K, Rb):
+        n_sets = math.ceil(R / Rb)
+        counts = np.full(n_sets, Rb, dtype=np.float64)
+        counts[-1] = R - (n_sets - 1) * Rb
+        fx, fy, w = ctx.sample_weights(samplers[name](), n_sets, K, psd, ap)
+        S = ctx.set_sf_expectation(K, fx, fy, w, n_sets, bx, by).cpu().numpy()
+        mean = counts @ S / R
+        return float(np.sqrt(np.mean((mean / an - 1.0) ** 2)))
 
-    out = {"L0": L0, "R": R, "R_block": R_block, "train_s": train_s,
-           "train_loss": [float(np.mean(loss[:20])), float(np.mean(loss[-20:]))]}
+    for Rb in (256, R):
+        tag = f"R_block={Rb}"
+        curves = {n: [e_s(n, K, Rb) for K in grid] for n in samplers}
+        block = {"E_S": curves, "by_target": {}}
+        for tgt in targets:
+            row = {}
+            for n in samplers:
+                ks = [K for K, e in zip(grid, curves[n]) if e <= tgt]
+                if not ks:
+                    row[n] = {"K": None}
+                    continue
+                K = ks[0]
+                row[n] = {"K": K}
+                for pname, prec in (("fp64", q.PREC_FP64), ("fp16x3", q.PREC_FP16X3)):
+                    res = {}
 
-    def run(name, sampler_fn, K, prec):
-        res = {}
-
-        def call():
-            res["sf"] = ctx.diff_piston_structure(psd, ap, bx, by, sampler_fn(), K, R, R_block,
-                                                  rng=q.Rng(7, 0, q.COEF_GAUSS_CS),
-                                                  precision=prec)[0]
-        ms = _time_call(call)
-        rel = res["sf"].cpu().numpy() / an - 1.0
-        out[name] = {"K": K, "precision": prec, "ms": ms, "realisations_per_s": R / (ms * 1e-3),
-                     "terms_per_s": R * K * cfg["bx"].size / (ms * 1e-3),
-                     "error_rms": float(np.sqrt(np.mean(rel ** 2))),
-                     "error_max": float(np.max(np.abs(rel)))}
-
-    run("plain_fp64_K65536", lambda: q.logpolar_sampler(cfg["fmin"], cfg["fmax"]), 65536,
-        q.PREC_FP64)
-    run("plain_bf16x6_K65536", lambda: q.logpolar_sampler(cfg["fmin"], cfg["fmax"]), 65536,
-        q.PREC_BF16X6)
-    run("plain_bf16x6_K4096", lambda: q.logpolar_sampler(cfg["fmin"], cfg["fmax"]), 4096,
-        q.PREC_BF16X6)
-    run("learned_bf16x6_K4096", lambda: q.learned_sampler(prop), 4096, q.PREC_BF16X6)
-    run("learned_splitbf16_K4096", lambda: q.learned_sampler(prop), 4096, q.PREC_SPLIT_BF16)
-    base = out["plain_fp64_K65536"]["realisations_per_s"]
-    for k in ("learned_bf16x6_K4096", "learned_splitbf16_K4096"):
-        out[k]["speedup_vs_plain_fp64"] = out[k]["realisations_per_s"] / base
+                    def call():
+                        res["sf"] = ctx.diff_piston_structure(
+                            psd, ap, bx, by, samplers[n](), K, R, Rb,
+                            rng=q.Rng(7, 0, q.COEF_GAUSS_CS), precision=prec)[0]
+                    ms = _time_call(call)
+                    rel = res["sf"].cpu().numpy() / an - 1.0
+                    row[n][pname] = {"ms": ms, "realisations_per_s": R / (ms * 1e-3),
+                                     "error_rms": float(np.sqrt(np.mean(rel ** 2))),
+                                     "error_max": float(np.max(np.abs(rel)))}
+            if row["plain"]["K"] and row["learned"]["K"]:
+                base = row["plain"]["fp64"]["realisations_per_s"]
+                row["speedup_learned_fp16x3_vs_plain_fp64"] = (
+                    row["learned"]["fp16x3"]["realisations_per_s"] / base)
+                row["speedup_learned_vs_plain_both_fp16x3"] = (
+                    row["learned"]["fp16x3"]["realisations_per_s"] /
+                    row["plain"]["fp16x3"]["realisations_per_s"])
+                row["speedup_plain_fp16x3_vs_plain_fp64"] = (
+                    row["plain"]["fp16x3"]["realisations_per_s"] / base)
+            block["by_target"][f"{tgt:.3%}"] = row
+        out["runs"][tag] = block
     prop.close()
     return out
 
@@ -247,59 +283,92 @@ def workload_phase(args):
 
 
 def workload_large_screen(args):
-    """Large screen: K = 65536, 256 x 256 points over 8 m, R = 4096, one
-    frequency set; the contraction in split-BF16, BF16x6 and FP32, each
-    checked against the FP64 oracle on realisations 0..63 at 1024 sampled
-    points (max and RMS phase error in rad).  Two-phase kernel (coefficient
-    tiles, then 256 x 256 MFMA tiles), and with --steps >= 2 the fused
-    kernel for comparison."""
+    """Large screen: K = 65536, 256 x 256 points over an 8 m square,
+    R = 4096, one frequency set, for r0 = 0.05, 0.1 and 0.2 m; the
+    contraction in split-BF16, BF16x6 and FP32 (two-phase kernel:
+    coefficient tiles, then 256 x 256 MFMA tiles) and FP16x3 (fused kernel),
+    each checked against the FP64 oracle on realisations 0..63 at 1024
+    sampled points (max and RMS phase error in rad), also reported for the
+    sampled points inside the circular pupil |x| <= 4 m; the pupil's own
+    point set (51 468 points) is timed too.  With --steps >= 2 the fused
+    kernel is timed for comparison at r0 = 0.1 m."""
     import numpy as np
     import torch
     import paper_2404_02978_amd as q
     import workloads
-    cfg = workloads.large_screen(r0=0.1)
-    K, R = cfg["K"], cfg["R"]
-    P = cfg["px"].size
-    ctx = q.Context(0)
-    px = torch.as_tensor(cfg["px"], device="cuda")
-    py = torch.as_tensor(cfg["py"], device="cuda")
-    s = q.logpolar_sampler(cfg["fmin"], cfg["fmax"])
-    fx, fy, area = ctx.sample_frequencies(s, 1, K)
-    w = ctx.weights(q.psd(cfg["r0"], cfg["L0"]), fx, fy, area)
-    hfx, hfy, hw = (t.cpu().numpy() for t in (fx, fy, w))
-    cols = np.random.default_rng(0).choice(P, 1024, replace=False)
-    rows = list(range(64))
     import oracle
-    t = time.perf_counter()
-    ref = oracle.synthesize(hfx, hfy, hw, cfg["px"][cols], cfg["py"][cols], 64, 64, K=K,
-                            seed=cfg["seed"])
-    oracle_s = time.perf_counter() - t
-    out = {"workload": "large screen, K=65536, 256x256 points over 8 m, R=4096, r0=0.1 m",
-           "flops": 4.0 * R * K * P, "oracle_subset_s": oracle_s, "runs": {}}
+    base = workloads.large_screen()
+    K, R = base["K"], base["R"]
+    P = base["px"].size
+    ctx = q.Context(0)
+    px = torch.as_tensor(base["px"], device="cuda")
+    py = torch.as_tensor(base["py"], device="cuda")
+    s = q.logpolar_sampler(base["fmin"], base["fmax"])
+    fx, fy, area = ctx.sample_frequencies(s, 1, K)
+    hfx, hfy = fx.cpu().numpy(), fy.cpu().numpy()
+    cols = np.random.default_rng(0).choice(P, 1024, replace=False)
+    inside = np.hypot(base["px"][cols], base["py"][cols]) <= 4.0
+    mask = np.hypot(base["px"], base["py"]) <= 4.0
+    mpx = torch.as_tensor(base["px"][mask], device="cuda")
+    mpy = torch.as_tensor(base["py"][mask], device="cuda")
+    cols_t = torch.as_tensor(cols, device="cuda")
+    out = {"workload": "large screen, K=65536, 256x256 points over 8 m, R=4096, "
+                       "r0 in {0.05, 0.1, 0.2} m, L0=25 m",
+           "flops": 4.0 * R * K * P, "pupil_points": int(mask.sum()), "runs": {}}
     phase = torch.empty((R, P), dtype=torch.float32, device="cuda")
-    for name, prec, passes, peak, path in (
-            ("split_bf16", q.PREC_SPLIT_BF16, 3, 2500.0, 2),
-            ("bf16x6", q.PREC_BF16X6, 6, 2500.0, 2),
-            ("fp32", q.PREC_FP32, 1, 157.3, 2),
-            ("split_bf16_fused", q.PREC_SPLIT_BF16, 3, 2500.0, 1),
-            ("bf16x6_fused", q.PREC_BF16X6, 6, 2500.0, 1),
-            ("fp32_fused", q.PREC_FP32, 1, 157.3, 1)):
-        if path == 1 and args.steps < 2:
-            continue
-        ctx.set_tuning(q.TUNE_WIDE_PATH, path)
+    mphase = torch.empty((R, int(mask.sum())), dtype=torch.float32, device="cuda")
+    for r0 in base["r0_list"]:
+        w = ctx.weights(q.psd(r0, base["L0"]), fx, fy, area)
+        hw = w.cpu().numpy()
+        t = time.perf_counter()
+        ref = oracle.synthesize(hfx, hfy, hw, base["px"][cols], base["py"][cols], 64, 64, K=K,
+                                seed=base["seed"])
+        oracle_s = time.perf_counter() - t
+        runs = {"oracle_subset_s": oracle_s, "phase_rms_rad": float(np.sqrt(np.mean(ref ** 2)))}
+        cases = [("split_bf16", q.PREC_SPLIT_BF16, 3, 2500.0, 2),
+                 ("bf16x6", q.PREC_BF16X6, 6, 2500.0, 2),
+                 ("fp32", q.PREC_FP32, 1, 157.3, 2),
+                 ("fp16x3_fused", q.PREC_FP16X3, 3, 2500.0, 1)]
+        if r0 == 0.1 and args.steps >= 2:
+            cases += [("split_bf16_fused", q.PREC_SPLIT_BF16, 3, 2500.0, 1),
+                      ("bf16x6_fused", q.PREC_BF16X6, 6, 2500.0, 1),
+                      ("fp32_fused", q.PREC_FP32, 1, 157.3, 1)]
+        for name, prec, passes, peak, path in cases:
+            ctx.set_tuning(q.TUNE_WIDE_PATH, path)
 
-        def call():
-            ctx.synthesize_phase(K, fx, fy, w, px, py, R, R, rng=q.Rng(cfg["seed"], 0, 0),
-                                 precision=prec, out=phase)
-        ms = _time_call(call, reps=3)
-        got = phase[:64][:, torch.as_tensor(cols, device="cuda")].double().cpu().numpy()
-        d = got - ref
-        alg = 4.0 * R * K * P / (ms * 1e-3) / 1e12
-        out["runs"][name] = {"ms": ms, "terms_per_s": R * K * P / (ms * 1e-3),
-                             "algorithmic_tflops": alg, "mfma_frac": alg * passes / peak,
-                             "max_abs_err_rad": float(np.max(np.abs(d))),
-                             "rms_abs_err_rad": float(np.sqrt(np.mean(d * d))),
-                             "phase_rms_rad": float(np.sqrt(np.mean(ref * ref)))}
+            def call():
+                ctx.synthesize_phase(K, fx, fy, w, px, py, R, R, rng=q.Rng(base["seed"], 0, 0),
+                                     precision=prec, out=phase)
+            ms = _time_call(call, reps=3)
+            got = phase[:64][:, cols_t].double().cpu().numpy()
+            d = got - ref
+            alg = 4.0 * R * K * P / (ms * 1e-3) / 1e12
+            runs[name] = {"ms": ms, "terms_per_s": R * K * P / (ms * 1e-3),
+                          "algorithmic_tflops": alg, "mfma_frac": alg / peak,
+                          "executed_mfma_frac": alg * passes / peak,
+                          "max_abs_err_rad": float(np.max(np.abs(d))),
+                          "rms_abs_err_rad": float(np.sqrt(np.mean(d * d))),
+                          "pupil_max_abs_err_rad": float(np.max(np.abs(d[:, inside]))),
+                          "pupil_rms_abs_err_rad": float(np.sqrt(np.mean(d[:, inside] ** 2)))}
+        # the circular pupil alone (split-BF16, two-phase kernel)
+        ctx.set_tuning(q.TUNE_WIDE_PATH, 2)
+
+        def call_mask():
+            ctx.synthesize_phase(K, fx, fy, w, mpx, mpy, R, R, rng=q.Rng(base["seed"], 0, 0),
+                                 precision=q.PREC_SPLIT_BF16, out=mphase)
+        ms = _time_call(call_mask, reps=3)
+        sel = np.flatnonzero(mask)
+        pos = np.searchsorted(sel, cols[inside])
+        got = mphase[:64][:, torch.as_tensor(pos, device="cuda")].double().cpu().numpy()
+        d = got - ref[:, inside]
+        runs["split_bf16_pupil_only"] = {
+            "ms": ms, "points": int(mask.sum()),
+            "terms_per_s": R * K * mask.sum() / (ms * 1e-3),
+            "max_abs_err_rad": float(np.max(np.abs(d))),
+            "rms_abs_err_rad": float(np.sqrt(np.mean(d * d)))}
+        out["runs"][f"r0={r0}"] = runs
+        print(json.dumps({f"r0={r0}": runs}), file=sys.stderr, flush=True)
+    ctx.set_tuning(q.TUNE_WIDE_PATH, 0)
     print(json.dumps(out), flush=True)
 
 
@@ -487,16 +556,16 @@ def main():
     if args.mode == "copy":
         copy_calibration()
         return
-    if args.workload != "diffpiston":
-        {"phase": workload_phase, "large_screen": workload_large_screen,
-         "batched": workload_batched, "temporal": workload_temporal,
-         "sampler_ablation": workload_sampler_ablation}[args.workload](args)
-        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
               "data-parallel over realisation blocks and is measured on a single MI355X.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload != "diffpiston":
+        {"phase": workload_phase, "large_screen": workload_large_screen,
+         "batched": workload_batched, "temporal": workload_temporal,
+         "sampler_ablation": workload_sampler_ablation}[args.workload](args)
+        return
     import numpy as np
     import torch
 
@@ -563,39 +632,47 @@ def main():
                                 "max": float(np.max(np.abs(rel)))}
 
     avg_kernel_ms = float(np.mean(kernel_ms))
-    flops = 4.0 * R * K * nB  # algorithmic: 2 MACs (cos and sin term) per (r, k, b)
+    # the method's work per launch: the contraction's 4 flops per term
+    # (2 MACs, cos and sin, per (r, k, b)), and, beside it, the vector work
+    # of its generator and basis (METHOD_OPS_*), without what the
+    # implementation adds (operand splits, basis rebuilt per row tile)
+    flops = 4.0 * R * K * nB
     achieved = flops / (avg_kernel_ms * 1e-3) / 1e12
-    peak = PEAKS[args.precision]
-    mfma_view = {"achieved": achieved * MFMA_PASSES[args.precision], "peak": peak,
-                 "unit": "TFLOP/s", "frac": achieved * MFMA_PASSES[args.precision] / peak,
-                 "algorithmic_tflops": achieved, "flops_per_launch": flops,
-                 "mfma_passes": MFMA_PASSES[args.precision]}
+    method_ops = (R * 2.0 * K * METHOD_OPS_PER_COEF
+                  + n_sets * K * nB * METHOD_OPS_PER_BASIS)
+    alu_view = {"achieved": method_ops / (avg_kernel_ms * 1e-3) / 1e12,
+                "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
+                "frac": method_ops / (avg_kernel_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                "ops_per_launch": method_ops,
+                "ops": f"{METHOD_OPS_PER_COEF} per coefficient (Philox4x32-10 10, uniform 2, "
+                       f"Box-Muller 4) + {METHOD_OPS_PER_BASIS} per (frequency, baseline, set)"}
     kern = ("k_sum_mfma<diff, sfsum> + k_sfsum_rows + k_reduce_sf (event-timed per launch on "
             "the stream they run on)")
     one_real = Rb == 1 and nB <= 64 and args.precision != "fp64"
     if one_real:
-        # one realisation per set: k_sf_one, FP32 on the vector ALU whatever
-        # the FP32-class precision (no operand split, no MFMA)
+        # one realisation per set: k_sf_one, binary32 FMAs on the vector ALU
+        # whatever the FP32-class precision (no operand split, no MFMA)
         kern = "k_sf_one + k_reduce_sf (event-timed per launch on the stream they run on)"
-        ops = R * 2.0 * K * OPS_PER_COEF_F32 + R * K * nB * OPS_PER_BASIS_ONE
-        a_ops = ops / (avg_kernel_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": a_ops, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": a_ops / VALU_PEAK_TOPS, "traffic": None, "ops_per_launch": ops,
-                "kernel": kern, "kernel_ms": avg_kernel_ms}
-    elif args.precision in OPS_PER_COEF:
-        # generator-bound: the coefficients are drawn by the vector ALU while
-        # the bf16 MFMAs run beside it on the matrix cores
-        row_tiles = math.ceil(Rb / 128)
-        ops = (R * 2.0 * K * OPS_PER_COEF[args.precision]
-               + n_sets * row_tiles * K * nB * OPS_PER_BASIS[args.precision])
-        a_ops = ops / (avg_kernel_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": a_ops, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": a_ops / VALU_PEAK_TOPS, "traffic": traffic_bytes(args, K, R, Rb),
-                "ops_per_launch": ops, "kernel": kern, "kernel_ms": avg_kernel_ms,
-                "mfma_view": mfma_view}
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK,
+                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
+                "flops_per_launch": flops, "kernel": kern, "kernel_ms": avg_kernel_ms,
+                "alu_view": alu_view}
+    elif args.precision == "fp64":
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": None,
+                "flops_per_launch": flops, "kernel": "k_sum_f64 + k_reduce_sf",
+                "kernel_ms": avg_kernel_ms, "alu_view": alu_view}
     else:
-        roof = dict(mfma_view, bound="mfma", traffic=traffic_bytes(args, K, R, Rb), kernel=kern,
-                    kernel_ms=avg_kernel_ms)
+        # the contraction on the matrix cores against the dense peak of its
+        # operand type; the generator on the vector ALU bounds the kernel
+        passes = MFMA_PASSES[args.precision]
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAKS[args.precision],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS[args.precision],
+                "traffic": traffic_bytes(args, K, R, Rb), "flops_per_launch": flops,
+                "kernel": kern, "kernel_ms": avg_kernel_ms,
+                "executed_mfma": {"passes": passes, "tflops": achieved * passes,
+                                  "frac": achieved * passes / PEAKS[args.precision]},
+                "alu_view": alu_view}
 
     # the same workload with the FP32 MFMA contraction, for reference
     fp32_ref = None
@@ -616,7 +693,7 @@ def main():
 
     compare = None
     if not args.no_compare:
-        compare = plain_vs_chosen(q, ctx, cfg)
+        compare = fixed_error(q, ctx, cfg)
 
     cpu = None
     if args.cpu_seconds > 0:
@@ -638,7 +715,7 @@ def main():
         "noise_floor_rms": math.sqrt(2.0 / R),
         "roofline": roof,
         "fp32_mfma_reference": fp32_ref,
-        "plain_vs_chosen": compare,
+        "fixed_error": compare,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

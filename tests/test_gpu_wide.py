@@ -204,18 +204,22 @@ def test_wide_policy(q):
         c.close()
 
 
+@pytest.mark.parametrize("r0", [0.05, 0.1, 0.2])
 @pytest.mark.parametrize("precision", PRECS)
-def test_wide_large_screen_sampled(q, precision):
+def test_wide_large_screen_sampled(q, precision, r0):
     """The 256 x 256-point, 8 m, K = 65536, R = 4096 screen in the launch
-    configuration the benchmark times (default policy): sampled realisations
-    and points against the oracle, including rows past the first
-    coefficient-tile piece."""
+    configuration the benchmark times (default policy), for each r0 of the
+    workload: sampled realisations and points against the oracle, including
+    rows past the first coefficient-tile piece; then the circular pupil
+    |x| <= 4 m alone as the point set, at sampled points."""
     cfg = workloads.large_screen()
     c = q.Context(0)
     try:
         K, R = cfg["K"], cfg["R"]
-        fx, fy, w = _freqs(c, q, 1, K, L0=cfg["L0"])
-        print(f"large screen p{precision}", flush=True)
+        s = q.logpolar_sampler(1e-3, 1e2)
+        fx, fy, area = c.sample_frequencies(s, 1, K)
+        w = c.weights(q.psd(r0, cfg["L0"]), fx, fy, area)
+        print(f"large screen p{precision} r0 {r0}", flush=True)
         out = c.synthesize_phase(K, fx, fy, w, dev(cfg["px"]), dev(cfg["py"]), R, R,
                                  rng=q.Rng(cfg["seed"], 0, 0), precision=precision)
         torch.cuda.synchronize()
@@ -223,12 +227,26 @@ def test_wide_large_screen_sampled(q, precision):
         cols = np.random.default_rng(0).choice(cfg["px"].size, 96, replace=False)
         got = out[torch.as_tensor(rows).cuda()][:, torch.as_tensor(cols).cuda()]
         got = host(got)
+        del out
         hfx, hfy, hw = host(fx), host(fy), host(w)
         ref = np.empty_like(got)
         for i, r in enumerate(rows):
             ref[i] = oracle.synthesize(hfx, hfy, hw, cfg["px"][cols], cfg["py"][cols], 1, 1,
                                        K=K, seed=cfg["seed"], counter=int(r))[0]
-        report(f"large screen p{precision}", got, ref, TOL[precision])
+        report(f"large screen p{precision} r0 {r0}", got, ref, TOL[precision])
+        # the circular pupil as the point set
+        mask = np.hypot(cfg["px"], cfg["py"]) <= 4.0
+        mx, my = cfg["px"][mask], cfg["py"][mask]
+        out = c.synthesize_phase(K, fx, fy, w, dev(mx), dev(my), R, R,
+                                 rng=q.Rng(cfg["seed"], 0, 0), precision=precision)
+        torch.cuda.synchronize()
+        mcols = np.random.default_rng(1).choice(mx.size, 64, replace=False)
+        got = host(out[torch.as_tensor(rows[:4]).cuda()][:, torch.as_tensor(mcols).cuda()])
         del out
+        ref = np.empty_like(got)
+        for i, r in enumerate(rows[:4]):
+            ref[i] = oracle.synthesize(hfx, hfy, hw, mx[mcols], my[mcols], 1, 1, K=K,
+                                       seed=cfg["seed"], counter=int(r))[0]
+        report(f"pupil p{precision} r0 {r0}", got, ref, TOL[precision])
     finally:
         c.close()
