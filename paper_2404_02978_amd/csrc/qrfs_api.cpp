@@ -933,6 +933,8 @@ qrfs_status qrfs_diff_piston_structure_sets_noalloc(qrfs_context* ctx, int64_t K
     if (sf_stderr && !aligned8(sf_stderr))
         return fail(QRFS_ERR_INVALID_ARG, "sf_stderr is not 8-byte aligned");
     if (!ctx) return fail(QRFS_ERR_INVALID_ARG, "context is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
     const qrfs::SfPlan plan = qrfs::sf_plan(precision, K, R, R_block, nB, kScratchBytes);
     const size_t need = qrfs::sf_plan_bytes(plan, nB);
     if (need > kScratchBytes)
@@ -942,8 +944,6 @@ qrfs_status qrfs_diff_piston_structure_sets_noalloc(qrfs_context* ctx, int64_t K
                     need, kScratchBytes);
     void* base = scratch_ptr(ctx->device);
     if (!base) return fail(QRFS_ERR_UNSUPPORTED, "no static scratch on device %d", ctx->device);
-    DeviceGuard g(ctx->device);
-    if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
     st = sf_sets_enqueue(plan, (char*)base, K, fx, fy, w, nB, bx, by, R, R_block, rng, precision,
                          sf, sf_stderr, (hipStream_t)stream);
     return st ? st : ok();

@@ -1121,6 +1121,27 @@ bool sf_one_realisation(int64_t R_block, int64_t P) { return R_block == 1 && P <
 
 static size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Blocks of the structure-function kernel the current device holds at once
+// (compute units x resident blocks per CU), for choosing the K split.
+static int64_t sf_resident_slots(int precision, int64_t R_block, int64_t P) {
+    const MfmaShape s = mfma_shape(precision, BASIS_DIFF, R_block, P);
+    const void* kern = nullptr;
+    if (precision == 1) kern = (const void*)k_sum_mfma<1, BASIS_DIFF, EPI_SFSUM, 1, 1, 0>;
+    else if (precision == 2) kern = (const void*)k_sum_mfma<2, BASIS_DIFF, EPI_SFSUM, 1, 1, 0>;
+    else if (precision == 3) kern = (const void*)k_sum_mfma<3, BASIS_DIFF, EPI_SFSUM, 1, 1, 0>;
+    else kern = (const void*)k_sum_mfma<4, BASIS_DIFF, EPI_SFSUM, 1, 1, 0>;
+    int dev = 0, ncu = 0, nb = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu < 1)
+        ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 64 * s.WV, 0) != hipSuccess ||
+        nb < 1)
+        nb = 1;
+    (void)hipGetLastError();
+    return (int64_t)ncu * nb;
+}
+
 size_t sf_plan_bytes(const SfPlan& p, int64_t P) {
     return round256((size_t)(p.n_partial_tiles * P) * 2 * sizeof(double)) +
            round256(p.phi_floats * sizeof(float));
@@ -1136,14 +1157,22 @@ SfPlan sf_plan(int precision, int64_t K, int64_t R, int64_t R_block, int64_t P,
     int64_t ks = 1;
     // one realisation per set: k_sf_one spreads the frequencies over a block
     if (precision != 0 && !sf_one_realisation(R_block, P)) {
-        // aim for >= 6 waves of blocks per resident slot (256 CUs x 4 blocks)
-        const int64_t target = 6 * 256 * 4;
+        // split K so that the blocks fill the chip's resident slots in whole
+        // rounds: the launch takes about ceil(base ks / slots) rounds of
+        // blocks 1/ks as long, plus the split-K partial sums' traffic (a
+        // few microseconds per range at these sizes)
+        const int64_t slots = sf_resident_slots(precision, R_block, P);
         const int64_t nch = cdiv(K, KC);
-        ks = cdiv(target, base);
-        if (ks > 16) ks = 16;
-        if (ks > nch / 2) ks = nch / 2;
-        if (ks < 1) ks = 1;
-        while (ks > 1 && (double)ks * R * P * 4.0 > (double)((size_t)1 << 30)) --ks;
+        int64_t kmax = nch / 2 < 16 ? nch / 2 : 16;
+        double best = 1e300;
+        for (int64_t k = 1; k <= (kmax < 1 ? 1 : kmax); ++k) {
+            if (k > 1 && (double)k * R * P * 4.0 > (double)((size_t)1 << 30)) break;
+            const double cost = (double)cdiv(base * k, slots) / (double)k + 0.003 * (double)k;
+            if (cost < best - 1e-12) {
+                best = cost;
+                ks = k;
+            }
+        }
     }
     for (;;) {
         p.ksplit = (int)ks;
