@@ -12,6 +12,18 @@
 
 namespace qrfs {
 
+// a * b + c in binary64 with the constant c taken from a scalar register
+// pair.  Polynomial steps written as fma() compile to v_fmac_f64, whose
+// addend is the destination: every constant coefficient then costs two
+// v_mov_b32 on the vector ALU before its FMA.  A v_fma_f64 reads the
+// coefficient from scalar registers that s_mov loads (scalar ALU, beside
+// the vector work): one vector instruction per step.
+__device__ __forceinline__ double fma_s(double a, double b, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
 // ---------------------------------------------------------------- R2 ----
 // Weyl increments of the 2-D R2 sequence (Sec. 3.2, Eq. 6):
 // round(2^64 / psi) and round(2^64 / psi^2), psi = 1.3247179572447460...
@@ -200,13 +212,166 @@ __device__ __forceinline__ double psd_phase(int model, double c, double r0_m53, 
     return c * r0_m53 * pow(q, -11.0 / 6.0);
 }
 
-// Circular aperture filter with central obstruction (Eq. 7), signed.
+// 2^y for |y| < 1000 in binary64: n = rint(y) comes off exactly and
+// 2^r = e^(r ln 2), |r| <= 1/2, is its Taylor series through r^13 (first
+// omitted term below 5e-18), summed by Horner's rule; then ldexp.  Within
+// 2 ulp of 2^y; no general-purpose exp with its range handling.
+constexpr double kExp2[14] = {
+    1.0, 0.6931471805599453, 0.24022650695910072, 0.05550410866482158,
+    0.009618129107628477, 0.0013333558146428443, 0.0001540353039338161, 1.5252733804059841e-05,
+    1.321548679014431e-06, 1.01780860092397e-07, 7.054911620801123e-09, 4.4455382718708116e-10,
+    2.5678435993488206e-11, 1.3691488853904128e-12};
+
+__device__ __forceinline__ double exp2_poly(double y) {
+    const double n = rint(y);
+    const double r = y - n;
+    double p = kExp2[13];
+#pragma unroll
+    for (int k = 12; k >= 0; --k) p = fma_s(p, r, kExp2[k]);
+    return ldexp(p, (int)n);
+}
+
+// sqrt(a) for a >= 0 in binary64 within 1 ulp: the hardware reciprocal
+// square-root estimate, two Newton steps on it, then one correction of
+// s = a y; 0 for a = 0.
+__device__ __forceinline__ double sqrt_nr(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+    const double h = 0.5 * a;
+    y = fma(y, fma(-h, y * y, 0.5), y);
+    y = fma(y, fma(-h, y * y, 0.5), y);
+    const double s = a * y;
+    const double r = fma(fma(-s, s, a), 0.5 * y, s);
+    return a > 0.0 ? r : 0.0;
+}
+
+// Fractional part of t to [-1/2, 1/2] in binary64 (exact).
+__device__ __forceinline__ double frac_centered(double t) { return t - rint(t); }
+
+// sin and cos of 2 pi r for an argument already reduced to |r| <= 1/2
+// revolutions, in FP64: q = rint(4 r) quarter turns come off exactly
+// (z = r - q/4, |z| <= 1/8, Sterbenz), the Taylor series of sin(2 pi z)
+// through z^15 and of cos(2 pi z) through z^16 (first omitted terms below
+// 7e-17 at |z| = 1/8) are summed by Horner's rule in z^2, and the quarter
+// turns are put back by an exact rotation.  Coefficients
+// (-1)^k (2 pi)^n / n!; max error 2e-16 (measured over [-1/2, 1/2]).
+constexpr double kSin2pi[8] = {
+    -0.71812230177850056, 3.819952584848282, -15.09464257682299, 42.058693944897655,
+    -76.705859753061389, 81.605249276075057, -41.341702240399762, 6.2831853071795862};
+constexpr double kCos2pi[9] = {
+    0.28200596845579123, -1.714390711088672, 7.9035363713184692, -26.426256783374399,
+    60.244641371876661, -85.456817206693728, 64.939394022668296, -19.739208802178716, 1.0};
+
+__device__ __forceinline__ void sincos2pi_reduced(double r, double& s, double& c) {
+    const double q = rint(4.0 * r);
+    const double z = fma(-0.25, q, r);
+    const double w = z * z;
+    double ps = kSin2pi[0];
+#pragma unroll
+    for (int n = 1; n < 8; ++n) ps = fma_s(ps, w, kSin2pi[n]);
+    ps *= z;
+    double pc = kCos2pi[0];
+#pragma unroll
+    for (int n = 1; n < 9; ++n) pc = fma_s(pc, w, kCos2pi[n]);
+    // the quarter turns: cos(pi q / 2) = 1 - |q| and sin(pi q / 2) =
+    // q (1 - |cos|) for |q| <= 2; one factor is 0 and the other +-1, so
+    // the rotation below is exact
+    const double cq = 1.0 - fabs(q);
+    const double sq = q * (1.0 - fabs(cq));
+    s = fma(ps, cq, pc * sq);
+    c = fma(pc, cq, -(ps * sq));
+}
+
+// J1(x) / x at x = pi t, t >= 0, for the aperture filter (Eq. 7): the
+// project's own binary64 Bessel function, from two published forms with
+// coefficients fitted by gen_bessel_j1.py (mpmath, 60 digits):
+//   x < 8:  a polynomial of degree 16 in x^2 - 32 (a fit of the entire
+//           function J1(sqrt z)/sqrt z, whose series is DLMF 10.2.2);
+//   x >= 8: Hankel's form (DLMF 10.17.3), J1(x) = sqrt(2/(pi x))
+//           (P cos chi - Q sin chi), chi = x - 3 pi/4, P and x Q / 8 as
+//           polynomials of degree 8 in (8/x)^2; chi / (2 pi) = t/2 - 3/8 is
+//           reduced exactly in revolutions (t = D f carries the argument
+//           without a product by pi).
+// Largest error against mpmath over t in [1e-4, 1e4]: 1.8e-15 in J1 (at
+// x ~ 9).  About 20 vector operations below x = 8 and 60 above, against
+// ~230 for the general-purpose j1.
+constexpr double kJ1Small[17] = {
+    -5.8143827955991070062e-2,
+    2.5330831370593110909e-3,
+    1.4796547991998664591e-4,
+    -7.9222065822122274542e-6,
+    1.5123726303789079841e-7,
+    -1.6315525237574344594e-9,
+    1.1601312451302481623e-11,
+    -5.9052821439999382497e-14,
+    2.2691399989608718142e-16,
+    -6.8342128144214883067e-19,
+    1.6595192217706221997e-21,
+    -3.3215324568230986011e-24,
+    5.5782364823880244287e-27,
+    -7.9770548836205354222e-30,
+    9.8345524159862802883e-33,
+    -1.0600016054226224458e-35,
+    1.0005202774655931299e-38};
+constexpr double kJ1P[9] = {
+    1.0000000000000063026,
+    1.8310546864401147473e-3,
+    -3.5203963650765904047e-5,
+    2.5806706940751284167e-6,
+    -4.0847900600833073724e-7,
+    1.0716140721535631355e-7,
+    -3.5134116038796300254e-8,
+    9.9892867642288659536e-9,
+    -1.5349264495380014555e-9};
+constexpr double kJ1Q[9] = {
+    4.6874999999994663438e-2,
+    -2.0027160554483289392e-4,
+    8.4709355706355412661e-6,
+    -9.5031068997007103812e-7,
+    2.0142935950325627865e-7,
+    -6.4943179103018863123e-8,
+    2.421946037301421181e-8,
+    -7.3884944031697531349e-9,
+    1.1785917506900844651e-9};
+
+__device__ __forceinline__ double j1x_pi(double t) {
+    const double x = 3.141592653589793 * t;
+    if (x < 8.0) {
+        const double z = fma(x, x, -32.0);
+        double acc = kJ1Small[16];
+#pragma unroll
+        for (int n = 15; n >= 0; --n) acc = fma_s(acc, z, kJ1Small[n]);
+        return acc;
+    }
+    // 1/x and 1/sqrt(x): hardware estimates and two Newton steps each
+    // (relative error ~1e-16, no full-precision division or square root)
+    double inv = __builtin_amdgcn_rcp(x);
+    inv = fma(fma(-x, inv, 1.0), inv, inv);
+    inv = fma(fma(-x, inv, 1.0), inv, inv);
+    double rs = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    rs = fma(rs, fma(-hx, rs * rs, 0.5), rs);
+    rs = fma(rs, fma(-hx, rs * rs, 0.5), rs);
+    const double w = 64.0 * inv * inv;
+    double p = kJ1P[8], q = kJ1Q[8];
+#pragma unroll
+    for (int n = 7; n >= 0; --n) {
+        p = fma_s(p, w, kJ1P[n]);
+        q = fma_s(q, w, kJ1Q[n]);
+    }
+    const double u = fma(0.5, t, -0.375);
+    double sn, cs;
+    sincos2pi_reduced(u - rint(u), sn, cs);
+    // sqrt(2 / (pi x)) / x (P cos chi - Q sin chi), Q = 8 q / x
+    return 0.79788456080286536 * rs * inv * fma(p, cs, -(8.0 * q * inv) * sn);
+}
+
+// Circular aperture filter with central obstruction (Eq. 7), signed:
+// F = 2 (D^2 J1(pi D f)/(pi D f) - d^2 J1(pi d f)/(pi d f)) / (D^2 - d^2).
 __device__ __forceinline__ double aperture_filter(double D, double d, double f) {
     if (f == 0.0) return 1.0;
-    const double pi = 3.141592653589793;
-    double num = D * j1(pi * D * f);
-    if (d > 0.0) num -= d * j1(pi * d * f);
-    return 2.0 * num / (pi * (D * D - d * d) * f);
+    if (d > 0.0)
+        return 2.0 * (D * D * j1x_pi(D * f) - d * d * j1x_pi(d * f)) / (D * D - d * d);
+    return 2.0 * j1x_pi(D * f);
 }
 
 // The same filter for the FP32-class paths, whose basis values are binary32:
@@ -221,46 +386,7 @@ __device__ __forceinline__ float aperture_filter_f32(double D, double d, double 
     return 2.0f * num / (float)(pi * (D * D - d * d) * f);
 }
 
-// Fractional part of t to [-1/2, 1/2] in binary64 (exact).
-__device__ __forceinline__ double frac_centered(double t) { return t - rint(t); }
 
-// sin and cos of 2 pi r for an argument already reduced to |r| <= 1/2
-// revolutions, in FP64: q = rint(4 r) quarter turns come off exactly
-// (z = r - q/4, |z| <= 1/8, Sterbenz), the Taylor series of sin(2 pi z)
-// through z^15 and of cos(2 pi z) through z^16 (first omitted terms below
-// 7e-17 at |z| = 1/8) are summed by Horner's rule in z^2, and the quarter
-// turns are put back by an exact rotation.  Coefficients
-// (-1)^k (2 pi)^n / n!; max error 2e-16 (measured over [-1/2, 1/2]).
-__device__ __forceinline__ void sincos2pi_reduced(double r, double& s, double& c) {
-    const double q = rint(4.0 * r);
-    const double z = fma(-0.25, q, r);
-    const double w = z * z;
-    double ps = -0.71812230177850056;
-    ps = fma(ps, w, 3.819952584848282);
-    ps = fma(ps, w, -15.09464257682299);
-    ps = fma(ps, w, 42.058693944897655);
-    ps = fma(ps, w, -76.705859753061389);
-    ps = fma(ps, w, 81.605249276075057);
-    ps = fma(ps, w, -41.341702240399762);
-    ps = fma(ps, w, 6.2831853071795862);
-    ps *= z;
-    double pc = 0.28200596845579123;
-    pc = fma(pc, w, -1.714390711088672);
-    pc = fma(pc, w, 7.9035363713184692);
-    pc = fma(pc, w, -26.426256783374399);
-    pc = fma(pc, w, 60.244641371876661);
-    pc = fma(pc, w, -85.456817206693728);
-    pc = fma(pc, w, 64.939394022668296);
-    pc = fma(pc, w, -19.739208802178716);
-    pc = fma(pc, w, 1.0);
-    // the quarter turns: cos(pi q / 2) = 1 - |q| and sin(pi q / 2) =
-    // q (1 - |cos|) for |q| <= 2; one factor is 0 and the other +-1, so
-    // the rotation below is exact
-    const double cq = 1.0 - fabs(q);
-    const double sq = q * (1.0 - fabs(cq));
-    s = fma(ps, cq, pc * sq);
-    c = fma(pc, cq, -(ps * sq));
-}
 
 // Piston basis: the amplitude factor and the argument shift (cycles) that
 // turn the piston into its gradient along u when `grad` is set, with

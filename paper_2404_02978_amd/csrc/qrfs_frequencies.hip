@@ -14,8 +14,8 @@ namespace qrfs {
 // map (3, 7), or placed in its cell of the jittered grid of Eq. 4 (4).
 __device__ __forceinline__ void sample_one(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
                                            int64_t i, int64_t K, int32_t N, double df, double L,
-                                           double fmin, double lr, double& fx, double& fy,
-                                           double& area) {
+                                           double fmin, double lr, double acoef, double& fx,
+                                           double& fy, double& area) {
     // no fused multiply-adds here or in weight_one: the values then do not
     // depend on the kernel they are inlined into
 #pragma clang fp contract(off)
@@ -28,7 +28,7 @@ __device__ __forceinline__ void sample_one(int scheme, uint64_t s0x, uint64_t s0
     if (map == 0) {
         fx = L * (ux - 0.5);
         fy = L * (uy - 0.5);
-        area = L * L / (double)K;
+        area = acoef;  // L^2 / K
     } else if (map == 4) {
         // Eq. 4: point k = iy N + ix of a set (K = N^2) at its cell's lower
         // corner -N df / 2 + i df plus the jitter u df, as df (i + u - N/2)
@@ -55,25 +55,27 @@ __device__ __forceinline__ void sample_one(int scheme, uint64_t s0x, uint64_t s0
         sincospi(ang, &s, &c);
         fx = L * rad * c;
         fy = L * rad * s;
-        area = 3.141592653589793 * L * L / (double)K;
+        area = acoef;  // pi L^2 / K
     } else {
-        double f = fmin * exp(lr * ux);
+        // |f| = fmin e^(lr u_x) = fmin 2^(lr log2(e) u_x), angle 2 pi u_y
+        // (u_y in [0, 1), reduced exactly)
+        double f = fmin * exp2_poly(lr * 1.4426950408889634 * ux);
         double s, c;
-        sincospi(2.0 * uy, &s, &c);
+        sincos2pi_reduced(uy - rint(uy), s, c);
         fx = f * c;
         fy = f * s;
-        area = 2.0 * 3.141592653589793 * lr * f * f / (double)K;
+        area = acoef * f * f;  // 2 pi lr f^2 / K
     }
 }
 
 __global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n,
                          int64_t K, int32_t N, double df, double L, double fmin, double lr,
-                         double* __restrict__ fx, double* __restrict__ fy,
+                         double acoef, double* __restrict__ fx, double* __restrict__ fy,
                          double* __restrict__ area) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double x, y, ar;
-    sample_one(scheme, s0x, s0y, index, i, K, N, df, L, fmin, lr, x, y, ar);
+    sample_one(scheme, s0x, s0y, index, i, K, N, df, L, fmin, lr, acoef, x, y, ar);
     fx[i] = x;
     fy[i] = y;
     area[i] = ar;
@@ -112,8 +114,8 @@ __device__ __forceinline__ double weight_one(int model, double c, double r0_m53,
 #pragma clang fp contract(off)
     const double f2 = x * x + y * y;
     const double q = f2 + (model == 1 ? inv_L02 : 0.0);
-    double v = q == 0.0 ? 0.0 : pow_m11_12(q) * sqrt(c * r0_m53 * area);
-    if (has_ap) v *= aperture_filter(D, d, sqrt(f2));
+    double v = q == 0.0 ? 0.0 : pow_m11_12(q) * sqrt_nr(c * r0_m53 * area);
+    if (has_ap) v *= aperture_filter(D, d, sqrt_nr(f2));
     return v;
 }
 
@@ -131,14 +133,15 @@ __global__ void k_weights(int model, double c, double r0_m53, double inv_L02, in
 // and re-reading the areas and the frequencies.
 __global__ void k_sample_weights(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
                                  int64_t n, int64_t K, int32_t N, double df, double L,
-                                 double fmin, double lr, int model, double c, double r0_m53,
+                                 double fmin, double lr, double acoef, int model, double c,
+                                 double r0_m53,
                                  double inv_L02, int has_ap, double D, double d,
                                  double* __restrict__ fx, double* __restrict__ fy,
                                  double* __restrict__ w) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double x, y, ar;
-    sample_one(scheme, s0x, s0y, index, i, K, N, df, L, fmin, lr, x, y, ar);
+    sample_one(scheme, s0x, s0y, index, i, K, N, df, L, fmin, lr, acoef, x, y, ar);
     fx[i] = x;
     fy[i] = y;
     w[i] = weight_one(model, c, r0_m53, inv_L02, has_ap, D, d, x, y, ar);
@@ -147,6 +150,18 @@ __global__ void k_sample_weights(int scheme, uint64_t s0x, uint64_t s0y, uint64_
 // ----------------------------------------------------------- launchers ----
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// The cell area of a set's points, or its factor: L^2 / K (Cartesian),
+// pi L^2 / K (disc), 2 pi ln(fmax/fmin) / K times f^2 (log-polar); the
+// jittered grid uses df^2.
+static double area_coef(int scheme, int64_t K, double L, double lr) {
+    const int map = scheme >= 5 ? (scheme == 7 ? 3 : scheme - 5) : scheme;
+    const double pi = 3.141592653589793;
+    if (map == 0) return L * L / (double)K;
+    if (map == 3) return pi * L * L / (double)K;
+    if (map == 1) return 2.0 * pi * lr / (double)K;
+    return 0.0;
+}
+
 hipError_t launch_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index, int64_t n_sets,
                          int64_t K, int32_t N, double df, double fmin, double fmax, double* fx,
                          double* fy, double* area, hipStream_t st) {
@@ -154,7 +169,7 @@ hipError_t launch_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
     double L = (scheme == 3 || scheme == 7) ? fmax : (double)N * df;
     double lr = (scheme == 1 || scheme == 6) ? log(fmax / fmin) : 0.0;
     hipLaunchKernelGGL(k_sample, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, scheme, s0x, s0y,
-                       index, n, K, N, df, L, fmin, lr, fx, fy, area);
+                       index, n, K, N, df, L, fmin, lr, area_coef(scheme, K, L, lr), fx, fy, area);
     return hipGetLastError();
 }
 
@@ -169,7 +184,7 @@ hipError_t launch_sample_weights(int scheme, uint64_t s0x, uint64_t s0y, uint64_
     double r0_m53 = pow(r0, -5.0 / 3.0);
     double inv_L02 = model == 1 ? 1.0 / (L0 * L0) : 0.0;
     hipLaunchKernelGGL(k_sample_weights, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, scheme,
-                       s0x, s0y, index, n, K, N, df, L, fmin, lr, model, c, r0_m53, inv_L02,
+                       s0x, s0y, index, n, K, N, df, L, fmin, lr, area_coef(scheme, K, L, lr), model, c, r0_m53, inv_L02,
                        has_ap, D, d, fx, fy, w);
     return hipGetLastError();
 }
