@@ -15,7 +15,7 @@ with the structure-function epilogue and its reduction.  Inputs are
 resident in HBM; nothing is copied to or from the host inside the timed
 region.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--precision fp16x3]
+  python bench.py [--gpus 1] [--steps 10] [--warmup 10] [--precision fp16x3]
   python bench.py --mode copy      (HBM counter calibration)
 """
 import argparse
@@ -46,19 +46,20 @@ PREC_IDS = {"fp64": 0, "fp32": 1, "split_bf16": 2, "bf16x6": 3, "fp16x3": 4}
 # MFMA FLOPs executed per algorithmic flop (split-BF16 runs 3 products, BF16x6 six)
 MFMA_PASSES = {"fp32": 1, "split_bf16": 3, "bf16x6": 6, "fp16x3": 3, "fp64": 1}
 DTYPES = {"fp32": "f32", "split_bf16": "bf16x3", "bf16x6": "bf16x6", "fp16x3": "fp16x3", "fp64": "f64"}
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
-# a 1 GiB copy (x2.0 / x1.0), valid only for the kernel source they were taken with
+# HBM bytes per launch of the timed kernel group (sum kernel, split-K row sums,
+# final reduction) from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a 1 GiB copy
+# (x2.0 / x1.0), valid only for the kernel source they were taken with
 # sources the structure-function kernels are built from (hashed together)
 KERNEL_SOURCES = ("qrfs_kernels.hip", "qrfs_mfma.hpp", "qrfs_device.hpp", "qrfs_internal.hpp")
-TRAFFIC = {"sha256_prefix": "2bddb9f8c57b9652", "K": 16384, "R": 100000, "R_block": 256,
-           "bytes": {"bf16x6": 2.563e8, "fp32": 2.563e8}}
+TRAFFIC = {"sha256_prefix": "24565a3508ab9a84", "K": 16384, "R": 100000, "R_block": 256,
+           "bytes": {"fp16x3": 5.240e8, "fp32": 6.478e8}}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=list(PREC_IDS), default="fp16x3")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: only a 1 GiB device-to-device copy, the reference for the "
@@ -464,7 +465,8 @@ def workload_temporal(args):
         out["runs"][name] = {"ms": ms, "realisations_per_s": R / (ms * 1e-3),
                              "terms_per_s": R * K * 2 * M / (ms * 1e-3),
                              "opd_um2": (sf[lags] * 1e12).tolist(),  # library gives m^2
-                             "z_vs_expected": ((sf[lags] - ex) / se[lags]).round(2).tolist()}
+                             "z_vs_expected": ((sf[lags] * 1e12 - ex * opd)
+                                               / (se[lags] * 1e12)).round(2).tolist()}
     print(json.dumps(out), flush=True)
 
 

@@ -282,10 +282,13 @@ __global__ __launch_bounds__(256) void k_sum_f64n(SumArgs a, int64_t col_tiles) 
 }
 
 // --------------------------------------------------------- MFMA kernel ----
-// One block = WV waves (WV = blockDim.x / 64 in 1..4).  Wave v owns rows
-// [32 MW v, 32 MW (v+1)) of the tile and all NT = 32 NB columns, so each
-// lane draws exactly the coefficients its own MFMA A-operand needs (no LDS
-// traffic for coefficients) while the basis tile is shared through LDS.
+// One block = WV waves (WV = blockDim.x / 64: 1..4, or 8 for the difference
+// basis of up to 32 baselines in the split precisions, so that one block
+// covers 256 rows and each set's basis is built once per 256 rows).  Wave v
+// owns rows [32 MW v, 32 MW (v+1)) of the tile and all NT = 32 NB columns,
+// so each lane draws exactly the coefficients its own MFMA A-operand needs
+// (no LDS traffic for coefficients) while the basis tile is shared through
+// LDS.
 // A block covers the frequency range [ks * kspan, (ks + 1) * kspan) of its
 // rows (split K: several blocks per row tile keep the grid balanced when
 // the rows alone do not fill the chip evenly).
@@ -308,8 +311,11 @@ __global__ __launch_bounds__(256) void k_sum_f64n(SumArgs a, int64_t col_tiles) 
 //     lo.hi), ~16 significant bits.  BF16x6: operands split three ways
 //     (hi + mid + lo, 24 bits) and six products (hi.hi, hi.mid, mid.hi,
 //     hi.lo, mid.mid, lo.hi), FP32-class.  BF16 keeps the FP32 exponent
-//     range, so no operand is ever subnormal.  Lane (r, h) holds
-//     coefficients j = 16 s + 8 h + 0..7, the natural order.
+//     range, so no operand is ever subnormal.  FP16x3: operands scaled by
+//     powers of two into the fp16 range and split two ways (fp16 hi + lo,
+//     22 bits), three v_mfma_f32_32x32x16_f16 products (hi.hi, hi.lo,
+//     lo.hi), FP32-class.  Lane (r, h) holds coefficients
+//     j = 16 s + 8 h + 0..7, the natural order.
 // FP32 MFMA runs on the vector datapath and never overlaps the VALU work of
 // the generator; the BF16 MFMAs run on the matrix cores and do.
 // The MFMA accumulators are added to a second FP32 accumulator after every
