@@ -595,8 +595,10 @@ def main():
 
     def step(record):
         for L0 in L0s:
-            # frequencies and weights in one pass (the cell areas are not needed)
-            fx, fy, w = ctx.sample_weights(sampler, n_sets, K, q.psd(cfg["r0"], L0), ap)
+            # frequencies and weights in one pass (the cell areas are not needed),
+            # the weights for sums in the precision of the step
+            fx, fy, w = ctx.sample_weights(sampler, n_sets, K, q.psd(cfg["r0"], L0), ap,
+                                           precision=cur["prec"])
             rng = q.Rng(cfg["seed"], counter[0], q.COEF_GAUSS_CS)
             counter[0] += R
             e0 = torch.cuda.Event(enable_timing=True)

@@ -70,7 +70,7 @@ typedef int32_t qrfs_status;
 #define QRFS_ERR_UNSUPPORTED (-4)   /* valid but not implemented combination  */
 #define QRFS_ERR_NOT_CONVERGED (-5) /* an iterative rule did not settle       */
 
-#define QRFS_ABI_VERSION 4
+#define QRFS_ABI_VERSION 5
 
 /* Static string for a status code. */
 QRFS_API const char* qrfs_error_string(qrfs_status s);
@@ -227,8 +227,9 @@ typedef struct {
  *   (All FP32-class precisions sum sets of at most 8 realisations on the
  *   vector ALU with this FP32 arithmetic: a matrix-core tile needs 32 rows.
  *   The split-BF16 and BF16x6 results are then those FP32 sums.  Their
- *   per-aperture filter of Eq. 7 (qrfs_piston, qrfs_tilt) is evaluated in
- *   binary32 like the basis it scales; FP64 evaluates it in binary64.)
+ *   per-aperture filter of Eq. 7 (qrfs_piston, qrfs_tilt) is evaluated to
+ *   binary32 accuracy like the basis it scales (the J1 of qrfs_weights'
+ *   FP32-class weights); FP64 evaluates it in binary64.)
  *   SPLIT_BF16  as FP32 but each operand is split into bf16 hi + lo and the
  *               contraction is hi.hi + hi.lo + lo.hi on bf16 MFMA with FP32
  *               accumulation (~16 significant bits); output float.
@@ -273,23 +274,32 @@ QRFS_API qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s,
  * the signed aperture filter F(|f|) when ap != NULL (piston of equal
  * apertures, Eq. 7).  All arrays double[n].  An exact f = 0 with the
  * Kolmogorov model contributes w = 0.
+ * precision: the precision of the sums the weights will feed.
+ *   QRFS_PREC_FP64: every step in binary64 (the PSD power within ~3e-16,
+ *   the filter's J1 within ~2e-15).
+ *   QRFS_PREC_FP32, _SPLIT_BF16, _BF16X6, _FP16X3: weights for FP32-class
+ *   sums, which round them to binary32 anyway: the PSD power within ~2e-12
+ *   and the filter from a shorter J1 with a binary32 Hankel branch
+ *   (absolute error ~1e-8 of the unfiltered weight); cheaper to evaluate.
  * Errors: n <= 0; NULL arrays; r0 <= 0; von Karman L0 <= 0; unknown model;
- * ap with D <= 0, d < 0 or d >= D. */
+ * ap with D <= 0, d < 0 or d >= D; unknown precision. */
 QRFS_API qrfs_status qrfs_weights(qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aperture* ap,
                          int64_t n, const double* fx, const double* fy, const double* area,
-                         double* w, void* stream);
+                         int32_t precision, double* w, void* stream);
 
 /* qrfs_sample_frequencies followed by qrfs_weights in one pass, for callers
  * that need the frequencies and their weights but not the cell areas
  * (Sec. 3.2, Eqs. 5-7): writes fx, fy (cycles/m) and w, all
- * double[n_sets*K], set-major, with the same values the two calls give.
- * ap == NULL: phase weights; else the filter of equal apertures is folded
- * in.  The learned sampler keeps its cell areas in the context's workspace
- * (grown to n_sets*K doubles if needed).  s->index += n_sets*K on success.
+ * double[n_sets*K], set-major, with the same values the two calls give
+ * (the same precision argument).  ap == NULL: phase weights; else the filter
+ * of equal apertures is folded in.  The learned sampler keeps its cell areas
+ * in the context's workspace (grown to n_sets*K doubles if needed).
+ * s->index += n_sets*K on success.
  * Errors: as qrfs_sample_frequencies and qrfs_weights. */
 QRFS_API qrfs_status qrfs_sample_weights(qrfs_context* ctx, qrfs_sampler* s, int64_t n_sets,
                                          int64_t K, const qrfs_psd* psd, const qrfs_aperture* ap,
-                                         double* fx, double* fy, double* w, void* stream);
+                                         int32_t precision, double* fx, double* fy, double* w,
+                                         void* stream);
 
 /* Hyper-parameters of the Cartesian sampler (Sec. 4.3), host-only (no
  * device work, no context): with g(x) = int_0^x f W(f) F(f)^2 df (F the

@@ -169,9 +169,9 @@ def load_library():
                                       ctypes.POINTER(ctypes.c_double)]),
         "qrfs_sample_frequencies": (S, [_P, ctypes.POINTER(Sampler), _I64, _I64, _P, _P, _P, _P]),
         "qrfs_weights": (S, [_P, ctypes.POINTER(Psd), ctypes.POINTER(Aperture), _I64, _P, _P, _P,
-                             _P, _P]),
+                             _I32, _P, _P]),
         "qrfs_sample_weights": (S, [_P, ctypes.POINTER(Sampler), _I64, _I64, ctypes.POINTER(Psd),
-                                    ctypes.POINTER(Aperture), _P, _P, _P, _P]),
+                                    ctypes.POINTER(Aperture), _I32, _P, _P, _P, _P]),
         "qrfs_synthesize_phase": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _I64, _I64,
                                       ctypes.POINTER(Rng), _P, _I32, _P, _P]),
         "qrfs_piston": (S, [_P, _I64, _P, _P, _P, _I64, _P, _P, _P, _P, _I64, _I64,
@@ -307,26 +307,28 @@ class Context:
                                                       _ptr(fx), _ptr(fy), _ptr(area), _stream()))
         return fx, fy, area
 
-    def sample_weights(self, sampler, n_sets, K, psd_, aperture=None):
+    def sample_weights(self, sampler, n_sets, K, psd_, aperture=None, precision=PREC_FP64):
         """Sampling and weights in one pass (no cell areas); returns
-        (fx, fy, w) float64 [n_sets*K]; advances sampler.index."""
+        (fx, fy, w) float64 [n_sets*K]; advances sampler.index.  precision:
+        that of the sums the weights feed (FP64: binary64 weights)."""
         n = n_sets * K
         fx = torch.empty(n, dtype=torch.float64, device=self.device)
         fy = torch.empty_like(fx)
         w = torch.empty_like(fx)
         ap = ctypes.byref(aperture) if aperture is not None else None
         _check(load_library().qrfs_sample_weights(self._h, ctypes.byref(sampler), n_sets, K,
-                                                  ctypes.byref(psd_), ap, _ptr(fx), _ptr(fy),
-                                                  _ptr(w), _stream()))
+                                                  ctypes.byref(psd_), ap, precision, _ptr(fx),
+                                                  _ptr(fy), _ptr(w), _stream()))
         return fx, fy, w
 
-    def weights(self, psd_, fx, fy, area, aperture=None):
+    def weights(self, psd_, fx, fy, area, aperture=None, precision=PREC_FP64):
         n = fx.numel()
         w = torch.empty(n, dtype=torch.float64, device=self.device)
         ap = ctypes.byref(aperture) if aperture is not None else None
         _check(load_library().qrfs_weights(self._h, ctypes.byref(psd_), ap, n,
                                            _dev_f64(fx, "fx"), _dev_f64(fy, "fy", n),
-                                           _dev_f64(area, "area", n), _ptr(w), _stream()))
+                                           _dev_f64(area, "area", n), precision, _ptr(w),
+                                           _stream()))
         return w
 
     def _out(self, R, P, precision):

@@ -11,6 +11,10 @@ F = 2 (D^2 J1(x_D)/x_D - d^2 J1(x_d)/x_d) / (D^2 - d^2), x = pi D f.
           x Q / 8 fitted as polynomials of degree 8 in w = (8/x)^2 in (0, 1],
           from P = sqrt(pi x/2) (J1 cos chi + Y1 sin chi) and
           Q = sqrt(pi x/2) (Y1 cos chi - J1 sin chi).
+For the FP32-class weights and basis values (j1x_pi_f32) the same two forms
+with fewer terms: the x < 8 polynomial of degree 10 (evaluated in binary64,
+fit error 1.2e-10) and P, x Q / 8 of degree 3 (evaluated in binary32, fit
+error 6e-11 in J1(x)/x).
 The reference values come from mpmath at 60 digits.  Run:
     python gen_bessel_j1.py      (prints the C++ constant tables)
 """
@@ -44,9 +48,10 @@ def large(deg=8, n=20):
     return lsq(ws, P, deg, lambda w: w), lsq(ws, q, deg, lambda w: w)
 
 
-def table(name, c):
-    body = ",\n    ".join(mp.nstr(v, 20, min_fixed=-1, max_fixed=-1) for v in c)
-    return f"constexpr double {name}[{len(c)}] = {{\n    {body}}};"
+def table(name, c, ctype="double", digits=20):
+    body = ",\n    ".join(mp.nstr(v, digits, min_fixed=-1, max_fixed=-1) +
+                          ("f" if ctype == "float" else "") for v in c)
+    return f"constexpr {ctype} {name}[{len(c)}] = {{\n    {body}}};"
 
 
 if __name__ == "__main__":
@@ -55,3 +60,7 @@ if __name__ == "__main__":
     print(table("kJ1Small", a))
     print(table("kJ1P", p))
     print(table("kJ1Q", q))
+    print(table("kJ1Small10", small(deg=10, n=18)))
+    p3, q3 = large(deg=3, n=11)
+    print(table("kJ1P3", p3, "float", 9))
+    print(table("kJ1Q3", q3, "float", 9))

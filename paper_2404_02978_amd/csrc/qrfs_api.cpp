@@ -220,20 +220,21 @@ hipError_t sample_any(const qrfs_sampler* s, uint64_t index, int64_t n_sets, int
 // Frequencies and weights of n_sets sets for a pipeline that needs no cell
 // areas: one fused kernel for the R2, pseudo-random and jittered samplers;
 // the learned sampler writes its areas to `area` and the weights follow.
+// f32: weights for FP32-class sums (qrfs_weights' precision argument).
 hipError_t sample_weights_any(const qrfs_sampler* s, uint64_t index, int64_t n_sets, int64_t K,
-                              const qrfs_psd* psd, double c, const qrfs_aperture* ap, double* fx,
-                              double* fy, double* area, double* w, hipStream_t st) {
+                              const qrfs_psd* psd, double c, const qrfs_aperture* ap, int f32,
+                              double* fx, double* fy, double* area, double* w, hipStream_t st) {
     const int has_ap = ap ? 1 : 0;
     const double D = ap ? ap->D : 0.0, d = ap ? ap->d : 0.0;
     if (s->scheme == QRFS_SAMPLER_LEARNED) {
         hipError_t e = sample_any(s, index, n_sets, K, fx, fy, area, st);
         if (e != hipSuccess) return e;
-        return qrfs::launch_weights(psd->model, c, psd->r0, psd->L0, has_ap, D, d, n_sets * K, fx,
-                                    fy, area, w, st);
+        return qrfs::launch_weights(psd->model, c, psd->r0, psd->L0, has_ap, D, d, f32,
+                                    n_sets * K, fx, fy, area, w, st);
     }
     return qrfs::launch_sample_weights(s->scheme, s->seed_x, s->seed_y, index, n_sets, K, s->N,
                                        s->df, s->fmin, s->fmax, psd->model, c, psd->r0, psd->L0,
-                                       has_ap, D, d, fx, fy, w, st);
+                                       has_ap, D, d, f32, fx, fy, w, st);
 }
 
 // Runs launch_sum over all sets, splitting the grid so no launch exceeds
@@ -517,12 +518,21 @@ qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s, int64_t 
     return ok();
 }
 
+// The precision argument of the weight entry points: any known precision,
+// FP64 for binary64 weights, the others for weights that feed FP32-class sums.
+static qrfs_status check_weight_precision(int32_t precision) {
+    if (precision < QRFS_PREC_FP64 || precision > QRFS_PREC_FP16X3)
+        return fail(QRFS_ERR_INVALID_ARG, "unknown precision %d", precision);
+    return QRFS_OK;
+}
+
 qrfs_status qrfs_weights(qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aperture* ap,
                          int64_t n, const double* fx, const double* fy, const double* area,
-                         double* w, void* stream) {
+                         int32_t precision, double* w, void* stream) {
     qrfs_status st = check_psd(psd);
     if (st) return st;
     if (ap && (st = check_ap(ap))) return st;
+    if ((st = check_weight_precision(precision))) return st;
     if (n <= 0) return fail(QRFS_ERR_INVALID_ARG, "n must be > 0 (got %lld)", (long long)n);
     CHECK_PTR(fx);
     CHECK_PTR(fy);
@@ -533,19 +543,21 @@ qrfs_status qrfs_weights(qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aper
     if (!g.okay) return fail(QRFS_ERR_DEVICE, "cannot select device %d", ctx->device);
     const double c = qrfs::psd_constant(psd->c, psd->wavelength);
     hipError_t e = qrfs::launch_weights(psd->model, c, psd->r0, psd->L0, ap ? 1 : 0,
-                                        ap ? ap->D : 0.0, ap ? ap->d : 0.0, n, fx, fy, area, w,
+                                        ap ? ap->D : 0.0, ap ? ap->d : 0.0,
+                                        precision != QRFS_PREC_FP64, n, fx, fy, area, w,
                                         (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "weights launch");
     return ok();
 }
 
 qrfs_status qrfs_sample_weights(qrfs_context* ctx, qrfs_sampler* s, int64_t n_sets, int64_t K,
-                                const qrfs_psd* psd, const qrfs_aperture* ap, double* fx,
-                                double* fy, double* w, void* stream) {
+                                const qrfs_psd* psd, const qrfs_aperture* ap, int32_t precision,
+                                double* fx, double* fy, double* w, void* stream) {
     qrfs_status st = check_sampler(s, K);
     if (st) return st;
     if ((st = check_psd(psd))) return st;
     if (ap && (st = check_ap(ap))) return st;
+    if ((st = check_weight_precision(precision))) return st;
     if (K <= 0 || n_sets <= 0)
         return fail(QRFS_ERR_INVALID_ARG, "K and n_sets must be > 0 (got %lld, %lld)",
                     (long long)K, (long long)n_sets);
@@ -564,7 +576,8 @@ qrfs_status qrfs_sample_weights(qrfs_context* ctx, qrfs_sampler* s, int64_t n_se
     }
     const double c = qrfs::psd_constant(psd->c, psd->wavelength);
     hipError_t e =
-        sample_weights_any(s, s->index, n_sets, K, psd, c, ap, fx, fy, area, w, (hipStream_t)stream);
+        sample_weights_any(s, s->index, n_sets, K, psd, c, ap, precision != QRFS_PREC_FP64, fx,
+                           fy, area, w, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "sampler / weights launch");
     s->index += (uint64_t)(n_sets * K);
     return ok();
@@ -654,8 +667,8 @@ qrfs_status qrfs_diff_piston_structure(qrfs_context* ctx, const qrfs_psd* psd,
     for (int64_t s0 = 0; s0 < n_sets; s0 += spb) {
         int64_t s1 = s0 + spb < n_sets ? s0 + spb : n_sets;
         int64_t ns = s1 - s0;
-        hipError_t e = sample_weights_any(s, s->index + (uint64_t)(s0 * K), ns, K, psd, c, ap, fx,
-                                          fy, area, w, stream_);
+        hipError_t e = sample_weights_any(s, s->index + (uint64_t)(s0 * K), ns, K, psd, c, ap, 0,
+                                          fx, fy, area, w, stream_);
         if (e != hipSuccess) return hip_fail(e, "sampler / weights launch");
         qrfs::SumArgs a{};
         a.K = K;
@@ -850,8 +863,8 @@ qrfs_status qrfs_temporal_piston_structure(qrfs_context* ctx, const qrfs_psd* ps
         const int64_t r0 = s0 * R_block;
         const int64_t rows = (s1 * R_block < R ? s1 * R_block : R) - r0;
         // equal apertures: the filter of Eq. 7 folds into the weight
-        e = sample_weights_any(s, s->index + (uint64_t)(s0 * K), ns, K, psd, c, ap, fx, fy, area,
-                               w, stream_);
+        e = sample_weights_any(s, s->index + (uint64_t)(s0 * K), ns, K, psd, c, ap, 0, fx, fy,
+                               area, w, stream_);
         if (e != hipSuccess) return hip_fail(e, "sampler / weights launch");
         // the piece as a problem of its own: realisations r0 .. r0 + rows
         qrfs::SumArgs a{};

@@ -267,7 +267,7 @@ qrfs_status enqueue(qrfs_batch* b, hipStream_t st) {
                                            b->area[i], st);
         if (e != hipSuccess) return hfail(e, "sampler launch");
         const double c = qrfs::psd_constant(in.psd.c, in.psd.wavelength);
-        e = qrfs::launch_weights(in.psd.model, c, in.psd.r0, in.psd.L0, 0, 0.0, 0.0,
+        e = qrfs::launch_weights(in.psd.model, c, in.psd.r0, in.psd.L0, 0, 0.0, 0.0, 0,
                                  b->n_sets[i] * in.K, b->fx[i], b->fy[i], b->area[i], b->w[i], st);
         if (e != hipSuccess) return hfail(e, "weights launch");
     }

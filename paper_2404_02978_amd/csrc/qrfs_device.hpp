@@ -244,6 +244,17 @@ __device__ __forceinline__ double sqrt_nr(double a) {
     return a > 0.0 ? r : 0.0;
 }
 
+// sqrt(a) for a >= 0 to ~1e-14 relative (not correctly rounded): the
+// binary32 reciprocal square root of a rounded to binary32, then one binary64
+// Newton correction of s = a y; sqrt_nr outside the binary32 range.  For
+// arguments that feed binary32-accuracy values (the FP32-class filter).
+__device__ __forceinline__ double sqrt_f32_nr(double a) {
+    if (!(a > 0x1p-120 && a < 0x1p120)) return sqrt_nr(a);
+    const double y = (double)__builtin_amdgcn_rsqf((float)a);
+    const double s = a * y;
+    return fma(fma(-s, s, a), 0.5 * y, s);
+}
+
 // Fractional part of t to [-1/2, 1/2] in binary64 (exact).
 __device__ __forceinline__ double frac_centered(double t) { return t - rint(t); }
 
@@ -374,16 +385,63 @@ __device__ __forceinline__ double aperture_filter(double D, double d, double f) 
     return 2.0 * j1x_pi(D * f);
 }
 
-// The same filter for the FP32-class paths, whose basis values are binary32:
-// the argument pi D f is formed in binary64 and rounded once, J1 is
-// evaluated in binary32 (absolute errors of a few 1e-8 where the filter is
-// large, tiny ones where it is small).
+// J1(x)/x at x = pi t for values that end in binary32 (FP32-class weights
+// and basis values), from the same two forms as j1x_pi with fewer terms
+// (tables from gen_bessel_j1.py): below x = 8 the polynomial of degree 10
+// in x^2 - 32, in binary64 (fit error 1.2e-10; as fast as binary32 here,
+// and free of the cancellation its terms would show in binary32); above,
+// Hankel's form with P and x Q / 8 of degree 3 in (8/x)^2 (fit error 6e-11)
+// in binary32, the phase t/2 - 3/8 reduced exactly in binary64 and the
+// hardware revolution sine and cosine.  Absolute error ~1e-8 (at x ~ 8,
+// from the binary32 amplitude and phase), i.e. relative to F(0) = 1.
+constexpr double kJ1Small10[11] = {
+    -5.8143827959149801797e-2,
+    2.5330830965939728592e-3,
+    1.4796548014204885492e-4,
+    -7.922205792102602279e-6,
+    1.5123726050846113425e-7,
+    -1.6315568427913620373e-9,
+    1.1601322986993743466e-11,
+    -5.9043187723429959103e-14,
+    2.2689416857908308261e-16,
+    -6.9281557493016852692e-19,
+    1.6767143093134783333e-21};
+constexpr float kJ1P3[4] = {1.0f, 1.83098991e-3f, -3.48635387e-5f, 1.97684287e-6f};
+constexpr float kJ1Q3[4] = {4.68749991e-2f, -2.00242639e-4f, 8.31696171e-6f, -6.70713004e-7f};
+
+__device__ __forceinline__ double j1x_pi_f32(double t) {
+    const double x = 3.141592653589793 * t;
+    if (x < 8.0) {
+        const double z = fma(x, x, -32.0);
+        double acc = kJ1Small10[10];
+#pragma unroll
+        for (int n = 9; n >= 0; --n) acc = fma_s(acc, z, kJ1Small10[n]);
+        return acc;
+    }
+    const float xf = (float)x;
+    const float inv = __builtin_amdgcn_rcpf(xf);
+    const float w = 64.0f * inv * inv;
+    float p = kJ1P3[3], q = kJ1Q3[3];
+#pragma unroll
+    for (int n = 2; n >= 0; --n) {
+        p = fmaf(p, w, kJ1P3[n]);
+        q = fmaf(q, w, kJ1Q3[n]);
+    }
+    const double u = fma(0.5, t, -0.375);
+    const float r = (float)(u - rint(u));
+    const float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
+    return (double)(0.79788456f * __builtin_amdgcn_rsqf(xf) * inv *
+                    fmaf(p, cs, -(8.0f * q * inv) * sn));
+}
+
+// The filter with j1x_pi_f32, for the FP32-class paths (weights that feed
+// binary32 sums, and the per-aperture basis values of pistons and tilts).
 __device__ __forceinline__ float aperture_filter_f32(double D, double d, double f) {
     if (f == 0.0) return 1.0f;
-    const double pi = 3.141592653589793;
-    float num = (float)D * j1f((float)(pi * D * f));
-    if (d > 0.0) num -= (float)d * j1f((float)(pi * d * f));
-    return 2.0f * num / (float)(pi * (D * D - d * d) * f);
+    if (d > 0.0)
+        return (float)(2.0 * (D * D * j1x_pi_f32(D * f) - d * d * j1x_pi_f32(d * f)) /
+                       (D * D - d * d));
+    return (float)(2.0 * j1x_pi_f32(D * f));
 }
 
 

@@ -88,10 +88,11 @@ __global__ void k_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
 // one square root fewer).
 // q^(-11/12) for q > 0 (the square root of the PSD's q^(-11/6)): q = 2^(12k) r
 // exactly with r in [2^-6, 2^6); a binary32 estimate of r^(-11/12) from the
-// hardware log2 / exp2 (relative error ~5e-7); two binary64 Newton steps on
-// y^12 r^11 = 1, y <- y (1 + (1 - y^12 r^11) / 12), each squaring the
-// relative error (to ~6e-13, then rounding); rescaled by 2^(-11k).  Within
-// ~3e-16 of the exact power of the rational exponent.
+// hardware log2 / exp2 (relative error ~5e-7); STEPS binary64 Newton steps
+// on y^12 r^11 = 1, y <- y (1 + (1 - y^12 r^11) / 12), each squaring the
+// relative error (one step: ~2e-12; two: within ~3e-16 of the exact power of
+// the rational exponent); rescaled by 2^(-11k).
+template <int STEPS>
 __device__ __forceinline__ double pow_m11_12(double q) {
     const int e = ilogb(q);
     const int k = (e + 6 + 1200) / 12 - 100;  // floor((e + 6) / 12)
@@ -100,7 +101,7 @@ __device__ __forceinline__ double pow_m11_12(double q) {
     double y = (double)__builtin_amdgcn_exp2f(-0.9166666865f * __builtin_amdgcn_logf(rf));
     const double r2 = r * r, r4 = r2 * r2, r11 = (r4 * r4) * (r2 * r);
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < STEPS; ++it) {
         const double y2 = y * y, y4 = y2 * y2;
         const double t = ((y4 * y4) * y4) * r11;
         y = fma(y, (1.0 - t) * (1.0 / 12.0), y);
@@ -108,29 +109,37 @@ __device__ __forceinline__ double pow_m11_12(double q) {
     return ldexp(y, -11 * k);
 }
 
+// F32: weights that feed binary32 sums (FP32-class precisions): the PSD
+// power to ~2e-12 and the filter by j1x_pi_f32 (absolute error ~1e-8 of the
+// unfiltered weight); otherwise every step in binary64.
+template <bool F32>
 __device__ __forceinline__ double weight_one(int model, double c, double r0_m53, double inv_L02,
                                              int has_ap, double D, double d, double x, double y,
                                              double area) {
 #pragma clang fp contract(off)
     const double f2 = x * x + y * y;
     const double q = f2 + (model == 1 ? inv_L02 : 0.0);
-    double v = q == 0.0 ? 0.0 : pow_m11_12(q) * sqrt_nr(c * r0_m53 * area);
-    if (has_ap) v *= aperture_filter(D, d, sqrt_nr(f2));
+    double v = q == 0.0 ? 0.0 : pow_m11_12<F32 ? 1 : 2>(q) * sqrt_nr(c * r0_m53 * area);
+    if (has_ap)
+        v *= F32 ? (double)aperture_filter_f32(D, d, sqrt_f32_nr(f2))
+                 : aperture_filter(D, d, sqrt_nr(f2));
     return v;
 }
 
+template <bool F32>
 __global__ void k_weights(int model, double c, double r0_m53, double inv_L02, int has_ap,
                           double D, double d, int64_t n, const double* __restrict__ fx,
                           const double* __restrict__ fy, const double* __restrict__ area,
                           double* __restrict__ w) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    w[i] = weight_one(model, c, r0_m53, inv_L02, has_ap, D, d, fx[i], fy[i], area[i]);
+    w[i] = weight_one<F32>(model, c, r0_m53, inv_L02, has_ap, D, d, fx[i], fy[i], area[i]);
 }
 
 // Both in one pass, for pipelines that need the weights but not the cell
 // areas: the same values as k_sample followed by k_weights, without writing
 // and re-reading the areas and the frequencies.
+template <bool F32>
 __global__ void k_sample_weights(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
                                  int64_t n, int64_t K, int32_t N, double df, double L,
                                  double fmin, double lr, double acoef, int model, double c,
@@ -144,7 +153,7 @@ __global__ void k_sample_weights(int scheme, uint64_t s0x, uint64_t s0y, uint64_
     sample_one(scheme, s0x, s0y, index, i, K, N, df, L, fmin, lr, acoef, x, y, ar);
     fx[i] = x;
     fy[i] = y;
-    w[i] = weight_one(model, c, r0_m53, inv_L02, has_ap, D, d, x, y, ar);
+    w[i] = weight_one<F32>(model, c, r0_m53, inv_L02, has_ap, D, d, x, y, ar);
 }
 
 // ----------------------------------------------------------- launchers ----
@@ -176,25 +185,27 @@ hipError_t launch_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
 hipError_t launch_sample_weights(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
                                  int64_t n_sets, int64_t K, int32_t N, double df, double fmin,
                                  double fmax, int model, double c, double r0, double L0,
-                                 int has_ap, double D, double d, double* fx, double* fy,
-                                 double* w, hipStream_t st) {
+                                 int has_ap, double D, double d, int f32, double* fx,
+                                 double* fy, double* w, hipStream_t st) {
     int64_t n = n_sets * K;
     double L = (scheme == 3 || scheme == 7) ? fmax : (double)N * df;
     double lr = (scheme == 1 || scheme == 6) ? log(fmax / fmin) : 0.0;
     double r0_m53 = pow(r0, -5.0 / 3.0);
     double inv_L02 = model == 1 ? 1.0 / (L0 * L0) : 0.0;
-    hipLaunchKernelGGL(k_sample_weights, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, scheme,
-                       s0x, s0y, index, n, K, N, df, L, fmin, lr, area_coef(scheme, K, L, lr), model, c, r0_m53, inv_L02,
-                       has_ap, D, d, fx, fy, w);
+    auto kern = f32 ? k_sample_weights<true> : k_sample_weights<false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, scheme, s0x, s0y,
+                       index, n, K, N, df, L, fmin, lr, area_coef(scheme, K, L, lr), model, c,
+                       r0_m53, inv_L02, has_ap, D, d, fx, fy, w);
     return hipGetLastError();
 }
 
 hipError_t launch_weights(int model, double c, double r0, double L0, int has_ap, double D,
-                          double d, int64_t n, const double* fx, const double* fy,
+                          double d, int f32, int64_t n, const double* fx, const double* fy,
                           const double* area, double* w, hipStream_t st) {
     double r0_m53 = pow(r0, -5.0 / 3.0);
     double inv_L02 = model == 1 ? 1.0 / (L0 * L0) : 0.0;
-    hipLaunchKernelGGL(k_weights, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, model, c, r0_m53,
+    auto kern = f32 ? k_weights<true> : k_weights<false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, model, c, r0_m53,
                        inv_L02, has_ap, D, d, n, fx, fy, area, w);
     return hipGetLastError();
 }

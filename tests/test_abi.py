@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(q):
 
 def test_abi_version_and_strings(q):
     lib = q.load_library()
-    assert lib.qrfs_abi_version() == 4
+    assert lib.qrfs_abi_version() == 5
     assert lib.qrfs_error_string(0) == b"success"
     assert lib.qrfs_error_string(-1) == b"invalid argument"
     assert lib.qrfs_error_string(-2) == b"out of device memory"
@@ -77,12 +77,14 @@ def test_argument_checks_precede_device_use(q):
     assert st == q.ERR_INVALID_ARG and b"context" in lib.qrfs_last_error_detail()
     # bad PSD / aperture
     psd = q.psd(0.1, -3.0)
-    st = lib.qrfs_weights(None, ctypes.byref(psd), None, 3, p, p, p, p, None)
+    st = lib.qrfs_weights(None, ctypes.byref(psd), None, 3, p, p, p, 0, p, None)
     assert st == q.ERR_INVALID_ARG and b"L0" in lib.qrfs_last_error_detail()
     ap = q.Aperture(1.0, 1.5)
-    st = lib.qrfs_weights(None, ctypes.byref(q.psd(0.1, 25.0)), ctypes.byref(ap), 3, p, p, p, p,
-                          None)
+    st = lib.qrfs_weights(None, ctypes.byref(q.psd(0.1, 25.0)), ctypes.byref(ap), 3, p, p, p, 0,
+                          p, None)
     assert st == q.ERR_INVALID_ARG
+    st = lib.qrfs_weights(None, ctypes.byref(q.psd(0.1, 25.0)), None, 3, p, p, p, -1, p, None)
+    assert st == q.ERR_INVALID_ARG and b"precision" in lib.qrfs_last_error_detail()
     # sampler checks
     s = q.logpolar_sampler(2.0, 1.0)
     st = lib.qrfs_sample_frequencies(None, ctypes.byref(s), 1, 8, p, p, p, None)
@@ -107,20 +109,23 @@ def test_argument_checks_precede_device_use(q):
     # then valid arguments reaching the NULL context (sampler index untouched)
     s = q.logpolar_sampler(2.0, 1.0)
     st = lib.qrfs_sample_weights(None, ctypes.byref(s), 1, 8, ctypes.byref(q.psd(0.1, 25.0)),
-                                 None, p, p, p, None)
+                                 None, 0, p, p, p, None)
     assert st == q.ERR_INVALID_ARG
     s = q.logpolar_sampler(1e-3, 1e2, index=5)
     st = lib.qrfs_sample_weights(None, ctypes.byref(s), 1, 8, ctypes.byref(q.psd(0.1, -1.0)),
-                                 None, p, p, p, None)
+                                 None, 0, p, p, p, None)
     assert st == q.ERR_INVALID_ARG and b"L0" in lib.qrfs_last_error_detail()
     st = lib.qrfs_sample_weights(None, ctypes.byref(s), 1, 8, ctypes.byref(q.psd(0.1, 25.0)),
-                                 ctypes.byref(q.Aperture(1.0, 1.0)), p, p, p, None)
+                                 ctypes.byref(q.Aperture(1.0, 1.0)), 0, p, p, p, None)
     assert st == q.ERR_INVALID_ARG
     st = lib.qrfs_sample_weights(None, ctypes.byref(s), 1, 8, ctypes.byref(q.psd(0.1, 25.0)),
-                                 None, p, p, None, None)
+                                 None, 0, p, p, None, None)
     assert st == q.ERR_INVALID_ARG
     st = lib.qrfs_sample_weights(None, ctypes.byref(s), 1, 8, ctypes.byref(q.psd(0.1, 25.0)),
-                                 None, p, p, p, None)
+                                 None, 7, p, p, p, None)
+    assert st == q.ERR_INVALID_ARG and b"precision" in lib.qrfs_last_error_detail()
+    st = lib.qrfs_sample_weights(None, ctypes.byref(s), 1, 8, ctypes.byref(q.psd(0.1, 25.0)),
+                                 None, 0, p, p, p, None)
     assert st == q.ERR_INVALID_ARG and b"context" in lib.qrfs_last_error_detail()
     assert s.index == 5
     # valid arguments, NULL context

@@ -180,10 +180,12 @@ def test_sampling_error_ordering(q, ctx):
 @pytest.mark.parametrize("scheme", ["cartesian", "logpolar", "disc", "jitter", "random_logpolar",
                                     "random_cartesian", "random_disc"])
 @pytest.mark.parametrize("ap", [None, (8.0, 1.1)])
-def test_sample_weights_equal_two_calls(q, ctx, scheme, ap):
+@pytest.mark.parametrize("precision", [0, 4])
+def test_sample_weights_equal_two_calls(q, ctx, scheme, ap, precision):
     """qrfs_sample_weights (one fused kernel) gives exactly the frequencies
-    and weights of qrfs_sample_frequencies followed by qrfs_weights, and
-    advances the sampler the same way."""
+    and weights of qrfs_sample_frequencies followed by qrfs_weights (binary64
+    weights, and those for FP32-class sums), and advances the sampler the
+    same way."""
     N, df, n_sets = 44, 0.25 / 22, 3
     K = N * N
     make = {
@@ -200,9 +202,9 @@ def test_sample_weights_equal_two_calls(q, ctx, scheme, ap):
     p = q.psd(0.1, 22.0)
     aperture = None if ap is None else q.Aperture(*ap)
     s1, s2 = make(), make()
-    fx, fy, w = ctx.sample_weights(s1, n_sets, K, p, aperture)
+    fx, fy, w = ctx.sample_weights(s1, n_sets, K, p, aperture, precision=precision)
     fx2, fy2, area = ctx.sample_frequencies(s2, n_sets, K)
-    w2 = ctx.weights(p, fx2, fy2, area, aperture)
+    w2 = ctx.weights(p, fx2, fy2, area, aperture, precision=precision)
     torch.cuda.synchronize()
     assert s1.index == s2.index == 9 + n_sets * K
     assert torch.equal(fx, fx2) and torch.equal(fy, fy2) and torch.equal(w, w2)
