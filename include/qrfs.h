@@ -278,9 +278,12 @@ QRFS_API qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s,
  *   QRFS_PREC_FP64: every step in binary64 (the PSD power within ~3e-16,
  *   the filter's J1 within ~2e-15).
  *   QRFS_PREC_FP32, _SPLIT_BF16, _BF16X6, _FP16X3: weights for FP32-class
- *   sums, which round them to binary32 anyway: the PSD power within ~2e-12
- *   and the filter from a shorter J1 with a binary32 Hankel branch
- *   (absolute error ~1e-8 of the unfiltered weight); cheaper to evaluate.
+ *   sums, which round them to binary32 anyway, with every factor to
+ *   binary32 accuracy: the PSD power within ~1e-7 (binary32 Newton step),
+ *   the square roots within ~1e-14, the filter from a shorter J1 with a
+ *   binary32 Hankel branch (absolute error ~3e-8 of the unfiltered
+ *   weight); cheaper to evaluate (mostly binary32 work instead of binary64).
+ *   The frequencies are the same in both modes.
  * Errors: n <= 0; NULL arrays; r0 <= 0; von Karman L0 <= 0; unknown model;
  * ap with D <= 0, d < 0 or d >= D; unknown precision. */
 QRFS_API qrfs_status qrfs_weights(qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aperture* ap,

@@ -31,14 +31,26 @@ __device__ __forceinline__ double fma_s(double a, double b, double c) {
 constexpr uint64_t kR2IncX = 0xC13FA9A902A6328FULL;
 constexpr uint64_t kR2IncY = 0x91E10DA5C79E7B1DULL;
 
+// A 0.64 fixed-point coordinate as the double (U >> 11) 2^-53 in [0, 1):
+// the high word times 2^-32 plus the low word without its 11 low bits times
+// 2^-64, both exact, and their sum has 53 significant bits, so the one
+// rounding of the fma is exact.
+__device__ __forceinline__ double r2_coord(uint64_t U) {
+    uint32_t hw = (uint32_t)(U >> 32);
+    // a plain 32-bit word to the conversion (seen as the top half of a
+    // 64-bit value, it is converted as one, with an extra add of zero)
+    asm("" : "+v"(hw));
+    const double hi = (double)hw;
+    const double lo = (double)((uint32_t)U & 0xfffff800u);
+    return fma(hi, 0x1p-32, lo * 0x1p-64);
+}
+
 // Point n (n >= 1) of the sequence started at (s0x, s0y) in 0.64 fixed
 // point, as doubles in [0,1) carrying the top 53 bits.
 __device__ __forceinline__ void r2_point(uint64_t s0x, uint64_t s0y, uint64_t n, double& ux,
                                          double& uy) {
-    uint64_t Ux = s0x + n * kR2IncX;
-    uint64_t Uy = s0y + n * kR2IncY;
-    ux = (double)(Ux >> 11) * 0x1p-53;
-    uy = (double)(Uy >> 11) * 0x1p-53;
+    ux = r2_coord(s0x + n * kR2IncX);
+    uy = r2_coord(s0y + n * kR2IncY);
 }
 
 // --------------------------------------------------------------- Philox ----

@@ -172,8 +172,8 @@ hipError_t launch_sample(int scheme, uint64_t s0x, uint64_t s0y, uint64_t index,
                          int64_t K, int32_t N, double df, double fmin, double fmax, double* fx,
                          double* fy, double* area, hipStream_t st);
 
-// f32: weights for FP32-class sums (the PSD power to ~2e-12, the filter by
-// the binary32-class J1); 0: every step in binary64.
+// f32: weights for FP32-class sums (every factor to binary32 accuracy, the
+// filter by the binary32-class J1); 0: every step in binary64.
 hipError_t launch_weights(int model, double c, double r0, double L0, int has_ap, double D,
                           double d, int f32, int64_t n, const double* fx, const double* fy,
                           const double* area, double* w, hipStream_t st);

@@ -468,7 +468,10 @@ __global__ __launch_bounds__(256) __attribute__((
     const int nb = (int)a.P;
     for (int b = tid; b < NPM; b += 256)
         sB[b] = b < nb ? make_double2(a.px[b], a.py[b]) : make_double2(0.0, 0.0);
-    __syncthreads();
+    // baselines along x (every y component zero, the usual layout of a
+    // structure function against baseline length): f.B is then the one
+    // product fx Bx, which is exactly what fx Bx + fy 0 rounds to
+    const bool along_x = __syncthreads_and(tid >= nb || a.py[tid < nb ? tid : 0] == 0.0);
     const double* fx = a.fx + sl * a.K;
     const double* fy = a.fy + sl * a.K;
     const double* w = a.w + sl * a.K;
@@ -515,13 +518,24 @@ __global__ __launch_bounds__(256) __attribute__((
             if constexpr (sizeof(T) == 4) {
                 const float fa = (float)amp;
                 const float ga = -2.0f * (g[2 * h] * fa), gb = g[2 * h + 1] * fa;
+                if (along_x) {
 #pragma unroll
-                for (int b = 0; b < NPM; ++b) {
-                    const double2 B = sB[b + z];
-                    const float r = (float)frac_centered(cfx * B.x + cfy * B.y);
-                    const float sh = __builtin_amdgcn_sinf(0.5f * r);  // sin(pi r)
-                    const float s2 = __builtin_amdgcn_sinf(r);         // sin(2 pi r)
-                    acc[b] = fmaf(ga, sh * sh, fmaf(gb, s2, acc[b]));
+                    for (int b = 0; b < NPM; ++b) {
+                        const double bx = sB[b + z].x;
+                        const float r = (float)frac_centered(cfx * bx);
+                        const float sh = __builtin_amdgcn_sinf(0.5f * r);  // sin(pi r)
+                        const float s2 = __builtin_amdgcn_sinf(r);         // sin(2 pi r)
+                        acc[b] = fmaf(ga, sh * sh, fmaf(gb, s2, acc[b]));
+                    }
+                } else {
+#pragma unroll
+                    for (int b = 0; b < NPM; ++b) {
+                        const double2 B = sB[b + z];
+                        const float r = (float)frac_centered(cfx * B.x + cfy * B.y);
+                        const float sh = __builtin_amdgcn_sinf(0.5f * r);  // sin(pi r)
+                        const float s2 = __builtin_amdgcn_sinf(r);         // sin(2 pi r)
+                        acc[b] = fmaf(ga, sh * sh, fmaf(gb, s2, acc[b]));
+                    }
                 }
             } else {
                 const double ga = -2.0 * (g[2 * h] * amp), gb = 2.0 * (g[2 * h + 1] * amp);

@@ -148,10 +148,11 @@ def test_weights(q, ctx, model, L0, ap):
 @pytest.mark.parametrize("model,L0,ap", [(1, 25.0, None), (1, 10.0, (1.8, 0.0)),
                                          (0, None, (8.0, 1.1))])
 def test_weights_fp32_class(q, ctx, precision, model, L0, ap):
-    """Weights for FP32-class sums: the PSD power to ~2e-12 (phase weights
-    within 1e-11 relative) and the filter from the shorter J1 with a binary32
-    Hankel branch, within 1e-7 of the unfiltered weight (a binary32 rounding
-    of the weight is 6e-8 of it)."""
+    """Weights for FP32-class sums, every factor to binary32 accuracy: phase
+    weights within 3e-7 relative (the PSD power's binary32 Newton step), the
+    filter from the shorter J1 with a binary32 Hankel branch within 1e-7 of
+    the unfiltered weight on top (a binary32 rounding of a weight is 6e-8 of
+    it)."""
     n_sets, K = 2, 1500
     s = q.logpolar_sampler(1e-3, 1e2)
     fx, fy, area = ctx.sample_frequencies(s, n_sets, K)
@@ -162,13 +163,10 @@ def test_weights_fp32_class(q, ctx, precision, model, L0, ap):
                          L0=L0 or 0.0, D=None if ap is None else ap[0],
                          d=0.0 if ap is None else ap[1])
     g = host(w)
-    if ap is None:
-        assert np.all(np.abs(g - ref) <= 1e-11 * np.abs(ref))
-        return
     w0 = oracle.weights(host(fx), host(fy), host(area), model=model, r0=0.1, L0=L0 or 0.0)
     err = np.abs(g - ref) / np.abs(w0)
     print(f"p{precision} ap={ap}: max |dw| / w0 = {err.max():.2e}")
-    assert np.all(err <= 1e-7)
+    assert np.all(err <= (3e-7 if ap is None else 4e-7))
 
 
 @pytest.mark.parametrize("D,d", [(1.8, 0.0), (8.0, 1.1), (39.0, 0.0)])
@@ -182,8 +180,10 @@ def test_weights_fp32_class_filter_range(q, ctx, D, d):
     w64 = host(ctx.weights(p, fx, fy, area, a))
     w32 = host(ctx.weights(p, fx, fy, area, a, precision=q.PREC_FP16X3))
     w0 = host(ctx.weights(p, fx, fy, area))
-    err = np.abs(w32 - w64) / w0
-    print(f"D={D} d={d}: max |dw| / w0 = {err.max():.2e}")
+    # the filter's own error, the common PSD factor's (<= 3e-7 relative) aside
+    f32, f64 = w32 / host(ctx.weights(p, fx, fy, area, precision=q.PREC_FP16X3)), w64 / w0
+    err = np.abs(f32 - f64)
+    print(f"D={D} d={d}: max |dF| = {err.max():.2e}")
     assert np.all(err <= 1e-7)
 
 

@@ -210,6 +210,26 @@ def test_sample_weights_equal_two_calls(q, ctx, scheme, ap, precision):
     assert torch.equal(fx, fx2) and torch.equal(fy, fy2) and torch.equal(w, w2)
 
 
+@pytest.mark.parametrize("ap,precision", [((1.8, 0.0), 0), ((8.0, 1.1), 0), ((1.8, 0.0), 4)])
+def test_sample_weights_lane_order_equal_two_calls(q, ctx, ap, precision):
+    """Large log-polar requests with binary64 weights and a filter run in
+    lane order (lanes of a wave 12096 indices apart, from 32 tiles of 774144
+    indices on): every frequency and weight equals the two-call result, over
+    33.9 tiles (the last one partly filled); the FP32-class weights of the
+    same request (plain order) too."""
+    n_sets, K = 1601, 16384
+    p = q.psd(0.1, 25.0)
+    aperture = q.Aperture(*ap)
+    s1 = q.logpolar_sampler(1e-3, 1e2, index=12345)
+    s2 = q.logpolar_sampler(1e-3, 1e2, index=12345)
+    fx, fy, w = ctx.sample_weights(s1, n_sets, K, p, aperture, precision=precision)
+    fx2, fy2, area = ctx.sample_frequencies(s2, n_sets, K)
+    w2 = ctx.weights(p, fx2, fy2, area, aperture, precision=precision)
+    torch.cuda.synchronize()
+    assert s1.index == s2.index == 12345 + n_sets * K
+    assert torch.equal(fx, fx2) and torch.equal(fy, fy2) and torch.equal(w, w2)
+
+
 def test_sample_weights_rejects_bad_arguments(q, ctx):
     with pytest.raises(q.QrfsError) as e:
         ctx.sample_weights(q.logpolar_sampler(2.0, 1.0), 1, 8, q.psd(0.1, 25.0))
