@@ -270,6 +270,13 @@ __device__ __forceinline__ double sqrt_f32_nr(double a) {
 // Fractional part of t to [-1/2, 1/2] in binary64 (exact).
 __device__ __forceinline__ double frac_centered(double t) { return t - rint(t); }
 
+// t - floor(t) in [0, 1) in binary64 (exact; one v_fract_f64), as binary32
+// revolutions for the hardware sine and cosine, which only need t modulo 1
+// (rounding error at most 2^-25 revolution).
+__device__ __forceinline__ float frac_rev_f32(double t) {
+    return (float)__builtin_amdgcn_fract(t);
+}
+
 // sin and cos of 2 pi r for an argument already reduced to |r| <= 1/2
 // revolutions, in FP64: q = rint(4 r) quarter turns come off exactly
 // (z = r - q/4, |z| <= 1/8, Sterbenz), the Taylor series of sin(2 pi z)

@@ -296,7 +296,7 @@ __global__ __launch_bounds__(256) void k_sum_f64n(SumArgs a, int64_t col_tiles) 
 // Per chunk of KC = 32 frequencies:
 //   - every thread evaluates the basis for one frequency (the next chunk's
 //     f, w are prefetched into registers one chunk ahead) and a few
-//     columns: t = f.x in FP64, r = t - rint(t), hardware sin/cos of 2 pi r
+//     columns: t = f.x in FP64, r = t - floor(t), hardware sin/cos of 2 pi r
 //     in FP32, times the weight (and the aperture filter for pistons);
 //     stored as [column][2 KC] floats (FP32) or as 16-bit hi and lo planes
 //     (split modes) in one of two LDS buffers, so one barrier per chunk
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(256) __attribute__((
 #pragma unroll
                     for (int b = 0; b < NPM; ++b) {
                         const double bx = sB[b + z].x;
-                        const float r = (float)frac_centered(cfx * bx);
+                        const float r = frac_rev_f32(cfx * bx);
                         const float sh = __builtin_amdgcn_sinf(0.5f * r);  // sin(pi r)
                         const float s2 = __builtin_amdgcn_sinf(r);         // sin(2 pi r)
                         acc[b] = fmaf(ga, sh * sh, fmaf(gb, s2, acc[b]));
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(256) __attribute__((
 #pragma unroll
                     for (int b = 0; b < NPM; ++b) {
                         const double2 B = sB[b + z];
-                        const float r = (float)frac_centered(cfx * B.x + cfy * B.y);
+                        const float r = frac_rev_f32(cfx * B.x + cfy * B.y);
                         const float sh = __builtin_amdgcn_sinf(0.5f * r);  // sin(pi r)
                         const float s2 = __builtin_amdgcn_sinf(r);         // sin(2 pi r)
                         acc[b] = fmaf(ga, sh * sh, fmaf(gb, s2, acc[b]));

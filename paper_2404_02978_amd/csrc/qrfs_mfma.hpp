@@ -110,9 +110,9 @@ __device__ __forceinline__ void f16_scale(double m, double& scale, float& unscal
 
 template <int BASIS>
 __device__ __forceinline__ void basis_pair(double t, double amp, float& cb, float& sb) {
-    float r = (float)frac_centered(t);
+    float r = frac_rev_f32(t);
     if (BASIS == BASIS_DIFF) {
-        float sh = __builtin_amdgcn_sinf(0.5f * r);  // sin(pi r)
+        float sh = __builtin_amdgcn_sinf(0.5f * r);  // sin(pi r), squared below
         cb = -2.0f * sh * sh;                         // cos(2 pi r) - 1
         sb = __builtin_amdgcn_sinf(r);
     } else {
