@@ -730,7 +730,9 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
             double amp = gw * (kAmp * wscale);
             if (BASIS == BASIS_PISTON) amp *= (double)aperture_filter_f32(sD[pp], sd[pp], fmag);
             float cb, sb;
-            basis_pair<BASIS>(cfx * spx[pp] + cfy * spy[pp] + sh, amp, cb, sb);
+            double t = cfx * spx[pp] + cfy * spy[pp];
+            if (BASIS == BASIS_PISTON) t += sh;  // (an add of 0 would not fold away)
+            basis_pair<BASIS>(t, amp, cb, sb);
             if constexpr (PREC == 1) {
                 float* dst = sBf + buf * NT * STR_F32 + pp * STR_F32 + 2 * kk;
                 dst[0] = cb;
