@@ -286,9 +286,9 @@ def workload_phase(args):
 def workload_large_screen(args):
     """Large screen: K = 65536, 256 x 256 points over an 8 m square,
     R = 4096, one frequency set, for r0 = 0.05, 0.1 and 0.2 m; the
-    contraction in split-BF16, BF16x6 and FP32 (two-phase kernel:
-    coefficient tiles, then 256 x 256 MFMA tiles) and FP16x3 (fused kernel),
-    each checked against the FP64 oracle on realisations 0..63 at 1024
+    contraction in split-BF16, FP16x3, BF16x6 and FP32 (two-phase kernel:
+    coefficient tiles, then 256 x 256 MFMA tiles), each checked against the
+    FP64 oracle on realisations 0..63 at 1024
     sampled points (max and RMS phase error in rad), also reported for the
     sampled points inside the circular pupil |x| <= 4 m; the pupil's own
     point set (51 468 points) is timed too.  With --steps >= 2 the fused
@@ -327,11 +327,12 @@ def workload_large_screen(args):
         oracle_s = time.perf_counter() - t
         runs = {"oracle_subset_s": oracle_s, "phase_rms_rad": float(np.sqrt(np.mean(ref ** 2)))}
         cases = [("split_bf16", q.PREC_SPLIT_BF16, 3, 2500.0, 2),
+                 ("fp16x3", q.PREC_FP16X3, 3, 2500.0, 2),
                  ("bf16x6", q.PREC_BF16X6, 6, 2500.0, 2),
-                 ("fp32", q.PREC_FP32, 1, 157.3, 2),
-                 ("fp16x3_fused", q.PREC_FP16X3, 3, 2500.0, 1)]
+                 ("fp32", q.PREC_FP32, 1, 157.3, 2)]
         if r0 == 0.1 and args.steps >= 2:
             cases += [("split_bf16_fused", q.PREC_SPLIT_BF16, 3, 2500.0, 1),
+                      ("fp16x3_fused", q.PREC_FP16X3, 3, 2500.0, 1),
                       ("bf16x6_fused", q.PREC_BF16X6, 6, 2500.0, 1),
                       ("fp32_fused", q.PREC_FP32, 1, 157.3, 1)]
         for name, prec, passes, peak, path in cases:

@@ -248,8 +248,12 @@ typedef struct {
  *               FP32-class accuracy (per-product error <= 2^-19 relative, an
  *               absolute floor of 2^-25 times the range's scale) with half
  *               the operand-split work and half the products of BF16X6.
- *               Fused kernel only: qrfs_synthesize_phase, qrfs_piston,
- *               qrfs_tilt, qrfs_diff_piston and the structure functions;
+ *               qrfs_synthesize_phase, qrfs_piston, qrfs_tilt,
+ *               qrfs_diff_piston and the structure functions; the two-phase
+ *               kernel for wide point sets scales each set's coefficient
+ *               tiles by one power of two (from its largest weight and the
+ *               largest coefficient the generators draw), so with
+ *               caller-given coefficients it contracts in the fused kernel;
  *               batches refuse it (QRFS_ERR_UNSUPPORTED); output float. */
 #define QRFS_PREC_FP64 0
 #define QRFS_PREC_FP32 1

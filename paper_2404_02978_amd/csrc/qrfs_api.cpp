@@ -267,9 +267,12 @@ qrfs_status run_sum(int precision, int basis, int epi, qrfs::SumArgs a, int64_t 
 // Whether the two-phase kernel contracts this problem: MFMA precisions,
 // outputs wide enough to amortise the coefficient tiles, and enough
 // 256 x 256 tiles to fill the chip (or forced by the context).
-bool use_wide(const qrfs_context* ctx, int precision, int64_t P, int64_t R, int64_t R_block) {
-    if (precision == QRFS_PREC_FP64 || precision == QRFS_PREC_FP16X3 || ctx->wide_path == 1)
-        return false;  // FP16X3 contracts in the fused kernel only
+bool use_wide(const qrfs_context* ctx, int precision, int64_t P, int64_t R, int64_t R_block,
+              bool caller_coef) {
+    if (precision == QRFS_PREC_FP64 || ctx->wide_path == 1) return false;
+    // FP16X3 scales the coefficient tiles by the largest value the generators
+    // can draw; caller-given coefficients contract in the fused kernel
+    if (precision == QRFS_PREC_FP16X3 && caller_coef) return false;
     if (P > ((int64_t)1 << 22)) return false;  // 256 rows of output within 32-bit tile offsets
     if (ctx->wide_path == 2) return true;
     const int64_t tiles = cdiv(R, R_block) * cdiv(R_block, 256) * cdiv(P, 256);
@@ -305,8 +308,15 @@ qrfs_status wide_sum(qrfs_context* ctx, int precision, int basis, qrfs::SumArgs 
         rows_piece = (tiles < 1 ? 1 : tiles) * 256;
     }
     const size_t tile_bytes = align256((size_t)sets_piece * cdiv(rows_piece, 256) * 8 * row32);
-    qrfs_status s = ensure_workspace(ctx, tile_bytes + 256);
+    const size_t scale_bytes =
+        precision == QRFS_PREC_FP16X3 ? align256((size_t)n_sets * sizeof(double)) : 0;
+    qrfs_status s = ensure_workspace(ctx, tile_bytes + 256 + scale_bytes);
     if (s) return s;
+    double* ascale = (double*)((char*)ctx->ws + tile_bytes + 256);
+    if (precision == QRFS_PREC_FP16X3) {
+        hipError_t e = qrfs::launch_wide_scale(a.w, a.K, n_sets, ascale, st);
+        if (e != hipSuccess) return hip_fail(e, "tile scale launch");
+    }
     // accumulation ranges: whole K for split-BF16, else about
     // ctx->range_freqs frequencies (an even number of chunks)
     int64_t rch = precision == QRFS_PREC_SPLIT_BF16 ? nch : cdiv(ctx->range_freqs, KCH);
@@ -330,6 +340,7 @@ qrfs_status wide_sum(qrfs_context* ctx, int precision, int basis, qrfs::SumArgs 
             wa.s.fx = fx0 + s0 * a.K;
             wa.s.fy = fy0 + s0 * a.K;
             wa.s.w = w0 + s0 * a.K;
+            wa.ascale = ascale + s0;
             wa.row_off = off;
             wa.rows = off + rows_piece < a.R_block ? rows_piece : a.R_block - off;
             wa.rts = cdiv(wa.rows, 256);
@@ -396,7 +407,7 @@ qrfs_status sum_entry(qrfs_context* ctx, int basis, int64_t K, const double* fx,
         a.gx = 2.0 * M_PI * grad_u[0];
         a.gy = 2.0 * M_PI * grad_u[1];
     }
-    if (use_wide(ctx, precision, P, R, R_block))
+    if (use_wide(ctx, precision, P, R, R_block, coef != nullptr))
         s = wide_sum(ctx, precision, basis, a, cdiv(R, R_block), (hipStream_t)stream);
     else
         s = run_sum(precision, basis, qrfs::EPI_STORE, a, cdiv(R, R_block), (hipStream_t)stream);

@@ -85,12 +85,17 @@ struct WideArgs {
     int32_t accumulate;  // 0: the first range stores its sums, 1: it adds them
     void* ctile;      // coefficient tiles
     float* sink;      // 64 floats that absorb the stores of elements outside the output
+    const double* ascale;  // FP16x3: per set of the launch, the power of two of its tiles
 };
 // frequencies per chunk of the two-phase kernel, and the bytes of
 // coefficient tiles per 32 rows for a padded contraction length nkv
 int wide_chunk(int precision);
 size_t wide_frag_bytes_per_row32(int precision, int64_t nkv);
 hipError_t launch_wide_coef(int precision, const WideArgs& wa, hipStream_t st);
+// FP16x3: per set, the power of two that scales its coefficient tiles into
+// the fp16 range (from the set's largest weight); n_sets blocks.
+hipError_t launch_wide_scale(const double* w, int64_t K, int64_t n_sets, double* ascale,
+                             hipStream_t st);
 hipError_t launch_wide_sum(int precision, int basis, const WideArgs& wa, hipStream_t st);
 
 // How the structure-function sums are split for a problem: ksplit

@@ -76,12 +76,62 @@ struct WideCfg<3> {  // BF16x6, 6 products
     typedef bf16x8 Frag;
 };
 
-int wide_chunk(int precision) { return precision == 1 ? 16 : precision == 2 ? 16 : 8; }
+template <>
+struct WideCfg<4> {  // FP16x3: fp16 hi + lo planes (coefficients scaled per set), 3 products
+    static constexpr int KCH = 16;
+    static constexpr int NPL = 2;
+    static constexpr int GF = 4;
+    static constexpr int KB = 16;
+    static constexpr int STR = 2 * KCH + 8;  // 80 B
+    typedef _Float16 T;
+    typedef f16x8 Frag;
+};
+
+int wide_chunk(int precision) { return precision == 3 ? 8 : 16; }
 
 size_t wide_frag_bytes_per_row32(int precision, int64_t nkv) {
     // one fragment (1 KiB) per plane per KB contraction values
     if (precision == 1) return (size_t)(nkv / 8) * 1024;
-    return (size_t)(nkv / 16) * 1024 * (precision == 2 ? 2 : 3);
+    return (size_t)(nkv / 16) * 1024 * (precision == 3 ? 3 : 2);
+}
+
+// The 16-bit operand planes of a split precision: bf16 (split-BF16, BF16x6)
+// or fp16 (FP16x3), and the matching MFMA.
+template <int PREC>
+__device__ __forceinline__ void split8_planes(const float (&v)[8],
+                                              typename WideCfg<PREC>::Frag (&o)[WideCfg<PREC>::NPL]) {
+    if constexpr (PREC == 4)
+        split8_f16(v, o);
+    else
+        split8_bf16<WideCfg<PREC>::NPL>(v, o);
+}
+__device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) { return mfma_bf16(a, b, c); }
+__device__ __forceinline__ f32x16 mfma16(f16x8 a, f16x8 b, f32x16 c) { return mfma_f16(a, b, c); }
+
+// FP16x3: the power of two that puts a set's largest coefficient-tile value
+// in [2^13, 2^14) (fp16 holds up to 65504): |w_k c_rk| <= max_k |w_k| times
+// the largest coefficient the generators can draw, 8.2 (Box-Muller radius
+// sqrt(-2 ln 2^-24) = 5.77 for the Gaussian pair, times sqrt(2) in the Eq. 3
+// form).  One block per set.
+constexpr double kCoefMax = 8.2;
+
+__global__ __launch_bounds__(256) void k_set_scale(const double* __restrict__ w, int64_t K,
+                                                   double* __restrict__ ascale) {
+    __shared__ double red[4];
+    const double* ws = w + (int64_t)blockIdx.x * K;
+    double m = 0.0;
+    for (int64_t k = threadIdx.x; k < K; k += 256) m = fmax(m, fabs(ws[k]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        double sc;
+        float us;
+        f16_scale(m * kCoefMax, sc, us);
+        ascale[blockIdx.x] = sc;
+    }
 }
 
 // ------------------------------------------------------ phase 1 ----
@@ -110,7 +160,8 @@ __global__ __launch_bounds__(256) void k_coef_tiles(WideArgs wa, int64_t n_threa
     const int h = lane >> 5;
     const int64_t twoK = 2 * a.K;
     const double* wk = a.w + sl * a.K;
-    constexpr int NV = C::KB / 2;  // values per lane: 4 (FP32) or 8 (BF16)
+    const double sc = PREC == 4 ? wa.ascale[sl] : 1.0;  // FP16x3: into the fp16 range
+    constexpr int NV = C::KB / 2;  // values per lane: 4 (FP32) or 8 (16-bit planes)
     const int64_t j0 = kb * C::KB + (int64_t)h * NV;
     float v[NV];
 #pragma unroll
@@ -135,7 +186,7 @@ __global__ __launch_bounds__(256) void k_coef_tiles(WideArgs wa, int64_t n_threa
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int64_t j = j0 + q + e;
-            v[q + e] = j < twoK ? (float)((double)g4[e] * wk[j >> 1]) : 0.0f;
+            v[q + e] = j < twoK ? (float)((double)g4[e] * wk[j >> 1] * sc) : 0.0f;
         }
     }
     const int64_t frag = (sl * wa.rt32 + rt) * NKB + kb;
@@ -143,10 +194,11 @@ __global__ __launch_bounds__(256) void k_coef_tiles(WideArgs wa, int64_t n_threa
         f32x4 o = {v[0], v[1], v[2], v[3]};
         ((f32x4*)wa.ctile)[frag * 64 + lane] = o;
     } else {
-        bf16x8 o[C::NPL];
-        split8_bf16<C::NPL>(v, o);
+        typedef typename C::Frag Frag;
+        Frag o[C::NPL];
+        split8_planes<PREC>(v, o);
 #pragma unroll
-        for (int p = 0; p < C::NPL; ++p) ((bf16x8*)wa.ctile)[(frag * C::NPL + p) * 64 + lane] = o[p];
+        for (int p = 0; p < C::NPL; ++p) ((Frag*)wa.ctile)[(frag * C::NPL + p) * 64 + lane] = o[p];
     }
 }
 
@@ -293,10 +345,10 @@ struct WideTile {
             f32x4 o = {v[0], v[1], v[2], v[3]};
             *(f32x4*)&sm.b[buf][0][col * STR + 4 * g] = o;
         } else {
-            bf16x8 o[NPL];
-            split8_bf16<NPL>(v, o);
+            Frag o[NPL];
+            split8_planes<PREC>(v, o);
 #pragma unroll
-            for (int p = 0; p < NPL; ++p) *(bf16x8*)&sm.b[buf][p][col * STR + 8 * g] = o[p];
+            for (int p = 0; p < NPL; ++p) *(Frag*)&sm.b[buf][p][col * STR + 8 * g] = o[p];
         }
     }
 
@@ -312,10 +364,10 @@ struct WideTile {
                     acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[mb][0][q], bv[q],
                                                                        acc[mb][nb], 0, 0, 0);
         } else {
-            bf16x8 bp[NPL];
+            Frag bp[NPL];
 #pragma unroll
             for (int p = 0; p < NPL; ++p)
-                bp[p] = *(const bf16x8*)&sm.b[buf][p][col * STR + 16 * st + 8 * h];
+                bp[p] = *(const Frag*)&sm.b[buf][p][col * STR + 16 * st + 8 * h];
             // product-major, so consecutive MFMAs update different
             // accumulators; smallest products first
             constexpr int NPR = NPL == 3 ? 6 : 3;
@@ -327,7 +379,7 @@ struct WideTile {
             for (int pr = 0; pr < NPR; ++pr)
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb)
-                    acc[mb][nb] = mfma_bf16(fa[mb][PA[pr + OFF]], bp[PB[pr + OFF]], acc[mb][nb]);
+                    acc[mb][nb] = mfma16(fa[mb][PA[pr + OFF]], bp[PB[pr + OFF]], acc[mb][nb]);
         }
     }
 
@@ -389,6 +441,16 @@ struct WideTile {
         asm volatile("" : "+v"(base), "+v"(rrem), "+v"(crem));
         float* o = (float*)a.out + base;
         float* sink = wa.sink + lane;
+        if constexpr (PREC == 4) {
+            // FP16x3: the coefficient tiles' power of two comes off exactly
+            const float us = (float)(1.0 / wa.ascale[sl]);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) acc[mb][nb][i] *= us;
+        }
         if (add) {
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb)
@@ -539,7 +601,14 @@ hipError_t launch_wide_coef(int precision, const WideArgs& wa, hipStream_t st) {
     if (precision == 1) return launch_coef_t<1>(wa, st);
     if (precision == 2) return launch_coef_t<2>(wa, st);
     if (precision == 3) return launch_coef_t<3>(wa, st);
+    if (precision == 4) return launch_coef_t<4>(wa, st);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_wide_scale(const double* w, int64_t K, int64_t n_sets, double* ascale,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_set_scale, dim3((unsigned)n_sets), dim3(256), 0, st, w, K, ascale);
+    return hipGetLastError();
 }
 
 
@@ -592,6 +661,7 @@ hipError_t launch_wide_sum(int precision, int basis, const WideArgs& wa, hipStre
     if (precision == 1) return launch_sum_p<1>(basis, wa, st);
     if (precision == 2) return launch_sum_p<2>(basis, wa, st);
     if (precision == 3) return launch_sum_p<3>(basis, wa, st);
+    if (precision == 4) return launch_sum_p<4>(basis, wa, st);
     return hipErrorInvalidValue;
 }
 

@@ -20,8 +20,8 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-TOL = {1: 1e-5, 2: 1e-3, 3: 1e-5}
-PRECS = [1, 2, 3]
+TOL = {1: 1e-5, 2: 1e-3, 3: 1e-5, 4: 1e-5}
+PRECS = [1, 2, 3, 4]
 
 
 @pytest.fixture(scope="module")
