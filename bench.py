@@ -395,7 +395,8 @@ def workload_batched(args):
                          py=torch.as_tensor(d["py"], device="cuda"), R=d["R"], R_block=d["R"],
                          rng=q.Rng(d["seed"], d["counter"], 0)))
     out = {"workload": "64 uneven phase-field instances, R=256 each", "runs": {}}
-    for name, prec in (("bf16x6", q.PREC_BF16X6), ("split_bf16", q.PREC_SPLIT_BF16)):
+    for name, prec in (("fp16x3", q.PREC_FP16X3), ("bf16x6", q.PREC_BF16X6),
+                       ("split_bf16", q.PREC_SPLIT_BF16)):
         b = q.Batch(ctx, inst, precision=prec)
         terms = b.info()["terms"]
         first_ms = _time_call(lambda: b.execute(), reps=1)
@@ -407,7 +408,7 @@ def workload_batched(args):
                              "first_call_ms": first_ms, "autotune_best_ms": tuned_ms,
                              "eager_ms": eager_ms, "graph_ms": graph_ms,
                              "terms_per_s_graph": terms / (graph_ms * 1e-3)}
-        if name == "bf16x6":
+        if name in ("fp16x3", "bf16x6"):
             j = int(np.argmax([d["K"] for d in specs]))
             d = specs[j]
             fxo, fyo, ao = oracle.sample_logpolar(1, d["K"], workloads.FMIN, workloads.FMAX,

@@ -254,7 +254,7 @@ typedef struct {
  *               tiles by one power of two (from its largest weight and the
  *               largest coefficient the generators draw), so with
  *               caller-given coefficients it contracts in the fused kernel;
- *               batches refuse it (QRFS_ERR_UNSUPPORTED); output float. */
+ *               batches take it on every launch shape; output float. */
 #define QRFS_PREC_FP64 0
 #define QRFS_PREC_FP32 1
 #define QRFS_PREC_SPLIT_BF16 2
@@ -625,8 +625,8 @@ typedef struct {
 typedef struct qrfs_batch qrfs_batch;
 
 /* Builds the work list of n instances (host array, copied).  precision:
- * QRFS_PREC_FP32, QRFS_PREC_SPLIT_BF16 or QRFS_PREC_BF16X6 (FP64 ->
- * QRFS_ERR_UNSUPPORTED).  Allocates the batch's device buffers.
+ * QRFS_PREC_FP32, QRFS_PREC_SPLIT_BF16, QRFS_PREC_BF16X6 or QRFS_PREC_FP16X3
+ * (FP64 -> QRFS_ERR_UNSUPPORTED).  Allocates the batch's device buffers.
  * Errors: n <= 0 or > 65535, any instance invalid as for
  * qrfs_synthesize_phase / qrfs_sample_frequencies / qrfs_weights /
  * qrfs_piston / qrfs_tilt; apD and apd not both NULL or both set; a

@@ -155,7 +155,12 @@ size_t wide_instance_bytes(const qrfs_batch* b, int i) {
 qrfs_status ensure_wide(qrfs_batch* b) {
     if (b->tiles) return QRFS_OK;
     if (!b->tile_bytes) return api_fail(QRFS_ERR_UNSUPPORTED, "two-phase shape unavailable");
-    hipError_t e = hipMalloc(&b->tiles, b->tile_bytes + 256);
+    // FP16x3: after the tiles and the 256-byte sink, one power of two per
+    // set of every instance (the scale of its coefficient tiles)
+    size_t scale_bytes = 0;
+    if (b->precision == QRFS_PREC_FP16X3)
+        for (int i = 0; i < b->n; ++i) scale_bytes += (size_t)b->n_sets[i] * sizeof(double);
+    hipError_t e = hipMalloc(&b->tiles, b->tile_bytes + 256 + scale_bytes);
     if (e == hipSuccess) e = hipMalloc(&b->d_wargs, sizeof(qrfs::WideArgs) * b->n);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -165,6 +170,7 @@ qrfs_status ensure_wide(qrfs_batch* b) {
     }
     const int KCH = qrfs::wide_chunk(b->precision);
     char* p = (char*)b->tiles;
+    double* scales = (double*)((char*)b->tiles + b->tile_bytes + 256);
     b->wargs.clear();
     for (int i = 0; i < b->n; ++i) {
         const qrfs_batch_instance& in = b->inst[i];
@@ -184,6 +190,10 @@ qrfs_status ensure_wide(qrfs_batch* b) {
         wa.accumulate = 0;
         wa.ctile = p;
         wa.sink = (float*)((char*)b->tiles + b->tile_bytes);
+        if (b->precision == QRFS_PREC_FP16X3) {
+            wa.ascale = scales;
+            scales += b->n_sets[i];
+        }
         p += wide_instance_bytes(b, i);
         b->wargs.push_back(wa);
     }
@@ -276,6 +286,11 @@ qrfs_status enqueue(qrfs_batch* b, hipStream_t st) {
     hipError_t e;
     if (sh.wide) {
         for (int i = 0; i < b->n; ++i) {
+            if (b->precision == QRFS_PREC_FP16X3) {
+                e = qrfs::launch_wide_scale(b->w[i], b->inst[i].K, b->n_sets[i],
+                                            (double*)b->wargs[i].ascale, st);
+                if (e != hipSuccess) return hfail(e, "tile scale launch");
+            }
             e = qrfs::launch_wide_coef(b->precision, b->wargs[i], st);
             if (e != hipSuccess) return hfail(e, "coefficient tile launch");
         }
@@ -357,10 +372,8 @@ qrfs_status qrfs_batch_create(qrfs_context* ctx, int64_t n, const qrfs_batch_ins
     if (!inst) return api_fail(QRFS_ERR_INVALID_ARG, "instances are NULL");
     if (precision == QRFS_PREC_FP64)
         return api_fail(QRFS_ERR_UNSUPPORTED, "batches run on the matrix cores (no FP64 path)");
-    if (precision == QRFS_PREC_FP16X3)
-        return api_fail(QRFS_ERR_UNSUPPORTED, "batches take FP32, split-BF16 or BF16x6");
     if (precision != QRFS_PREC_FP32 && precision != QRFS_PREC_SPLIT_BF16 &&
-        precision != QRFS_PREC_BF16X6)
+        precision != QRFS_PREC_BF16X6 && precision != QRFS_PREC_FP16X3)
         return api_fail(QRFS_ERR_INVALID_ARG, "unknown precision %d", precision);
     for (int64_t i = 0; i < n; ++i) {
         qrfs_status s = check_instance(inst[i], i);

@@ -1386,6 +1386,8 @@ hipError_t launch_batch(int precision, BatchShape shape, bool has_ap, const SumA
         return launch_batch_p<1>(MW, NB, has_ap, inst, items, n_items, counter, n_blocks, st);
     if (precision == 2)
         return launch_batch_p<2>(MW, NB, has_ap, inst, items, n_items, counter, n_blocks, st);
+    if (precision == 4)
+        return launch_batch_p<4>(MW, NB, has_ap, inst, items, n_items, counter, n_blocks, st);
     return launch_batch_p<3>(MW, NB, has_ap, inst, items, n_items, counter, n_blocks, st);
 }
 

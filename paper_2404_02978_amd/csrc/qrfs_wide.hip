@@ -653,6 +653,8 @@ hipError_t launch_wide_batch(int precision, bool has_ap, const WideArgs* inst,
         return launch_wide_batch_t<2>(has_ap, inst, items, n_items, counter, n_blocks, st);
     if (precision == 3)
         return launch_wide_batch_t<3>(has_ap, inst, items, n_items, counter, n_blocks, st);
+    if (precision == 4)
+        return launch_wide_batch_t<4>(has_ap, inst, items, n_items, counter, n_blocks, st);
     return hipErrorInvalidValue;
 }
 

@@ -12,7 +12,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-TOL = {1: 1e-5, 2: 1e-3, 3: 1e-5}
+TOL = {1: 1e-5, 2: 1e-3, 3: 1e-5, 4: 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -61,7 +61,7 @@ def check(outs, refs, tol, tag):
         assert e <= tol, (tag, i, e)
 
 
-@pytest.mark.parametrize("precision", [1, 2, 3])
+@pytest.mark.parametrize("precision", [1, 2, 3, 4])
 @pytest.mark.parametrize("R_block_div", [1, 3])
 def test_batch_matches_oracle(q, ctx, precision, R_block_div):
     inst, refs = instances(q, R_block_div)
@@ -72,7 +72,7 @@ def test_batch_matches_oracle(q, ctx, precision, R_block_div):
     b.close()
 
 
-@pytest.mark.parametrize("precision", [1, 2, 3])
+@pytest.mark.parametrize("precision", [1, 2, 3, 4])
 @pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
 def test_batch_every_shape(q, ctx, precision, shape):
     """Each launch shape (fused 0-3, two-phase 4) against the oracle, with
@@ -83,13 +83,6 @@ def test_batch_every_shape(q, ctx, precision, shape):
     assert b.info()["shape"] == shape
     check(b.execute(), refs, TOL[precision], f"shape {shape} p{precision}")
     b.close()
-
-
-def test_batch_refuses_fp16x3(q, ctx):
-    inst, _ = instances(q, 1)
-    with pytest.raises(q.QrfsError) as e:
-        q.Batch(ctx, inst, precision=q.PREC_FP16X3)
-    assert e.value.status == q.ERR_UNSUPPORTED
 
 
 def test_batch_two_phase_is_default(q, ctx):
@@ -152,7 +145,7 @@ def test_batch_autotune(q, ctx):
     b.close()
 
 
-@pytest.mark.parametrize("precision", [3, 2])
+@pytest.mark.parametrize("precision", [4, 3, 2])
 def test_batch_full_size_graph(q, ctx, precision):
     """The 64 uneven instances of the benchmark (R = 256 each, K up to 65536,
     grids up to 512^2 masked to the disk) in its timed configuration:
@@ -249,7 +242,7 @@ def aperture_instances(q):
     return inst, refs
 
 
-@pytest.mark.parametrize("precision", [1, 2, 3])
+@pytest.mark.parametrize("precision", [1, 2, 3, 4])
 @pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
 def test_batch_apertures_every_shape(q, ctx, precision, shape):
     inst, refs = aperture_instances(q)
