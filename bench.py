@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--R", type=int, default=100000)
     ap.add_argument("--K", type=int, default=16384)
     ap.add_argument("--R-block", type=int, default=256)
+    ap.add_argument("--range-freqs", type=int, default=0,
+                    help="large_screen: frequencies per FP32-class accumulation range of the "
+                         "two-phase kernel (0: the library's default, 2048)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle sample (0 disables it)")
     ap.add_argument("--no-compare", action="store_true",
@@ -315,7 +318,8 @@ def workload_large_screen(args):
     cols_t = torch.as_tensor(cols, device="cuda")
     out = {"workload": "large screen, K=65536, 256x256 points over 8 m, R=4096, "
                        "r0 in {0.05, 0.1, 0.2} m, L0=25 m",
-           "flops": 4.0 * R * K * P, "pupil_points": int(mask.sum()), "runs": {}}
+           "flops": 4.0 * R * K * P, "pupil_points": int(mask.sum()),
+           "range_freqs": args.range_freqs or 2048, "runs": {}}
     phase = torch.empty((R, P), dtype=torch.float32, device="cuda")
     mphase = torch.empty((R, int(mask.sum())), dtype=torch.float32, device="cuda")
     for r0 in base["r0_list"]:
@@ -337,6 +341,8 @@ def workload_large_screen(args):
                       ("fp32_fused", q.PREC_FP32, 1, 157.3, 1)]
         for name, prec, passes, peak, path in cases:
             ctx.set_tuning(q.TUNE_WIDE_PATH, path)
+            if args.range_freqs:
+                ctx.set_tuning(q.TUNE_RANGE_FREQS, args.range_freqs)
 
             def call():
                 ctx.synthesize_phase(K, fx, fy, w, px, py, R, R, rng=q.Rng(base["seed"], 0, 0),

@@ -42,6 +42,9 @@ constexpr int WT = 256;  // rows and columns of a block tile
 #ifndef QRFS_WIDE_PHASE
 #define QRFS_WIDE_PHASE 1
 #endif
+#ifndef QRFS_WIDE_ATOMIC_ADD
+#define QRFS_WIDE_ATOMIC_ADD 1
+#endif
 
 template <int PREC>
 struct WideCfg;
@@ -460,8 +463,16 @@ struct WideTile {
                     for (int i = 0; i < 16; ++i) {
                         const int c = mb * 32 + 8 * (i / 4) + (i % 4);
                         const bool ok = c < rrem && nb * 32 < crem;
+#if QRFS_WIDE_ATOMIC_ADD
+                        // posted float atomic adds (no return value): the
+                        // block goes on with the next range while they drain.
+                        // Each element is added to by one lane only, in
+                        // program order, so the sums are deterministic.
+                        if (ok) unsafeAtomicAdd(o + (int64_t)c * a.P + nb * 32, acc[mb][nb][i]);
+#else
                         float* p = ok ? o + (int64_t)c * a.P + nb * 32 : sink;
                         *p += acc[mb][nb][i];
+#endif
                     }
         } else {
 #pragma unroll
