@@ -741,7 +741,7 @@ __device__ __forceinline__ void sum_tile(const SumArgs& a, int64_t row_tiles, in
                 const int o = buf * NT * STR_H + pp * STR_H + 2 * kk;  // even
                 uint32_t pcs[NPL];
                 if constexpr (PREC == 4)
-                    split_f16x2(cb, sb, pcs);
+                    split_f16x2<true>(cb, sb, pcs);
                 else
                     split_bf16x2<NPL>(cb, sb, pcs);
 #pragma unroll

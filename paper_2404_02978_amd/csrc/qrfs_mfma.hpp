@@ -55,12 +55,16 @@ __device__ __forceinline__ void split8_bf16(const float (&v)[8], bf16x8 (&o)[NPL
 }
 
 // FP16x3 operands: x = hi + lo in fp16.  hi is x rounded to nearest fp16,
-// the remainder x - hi is exact in binary32 (one v_fma_mix_f32 that takes
-// hi as an fp16 operand: no conversion back), and lo is its rounding:
+// the remainder x - hi is exact in binary32, and lo is its rounding:
 // |x - hi - lo| <= 2^-22 |x| in the normal fp16 range and below 2^-25
 // absolute where hi or lo is an fp16 subnormal.  The caller keeps
 // |x| < 2^15.  Two values at once: hi and lo each as one packed word,
 // x0 in the low half (the element order of the MFMA operands).
+// Two forms with the same values: FEW forms the remainder with one
+// v_fma_mix_f32 per value that reads hi as an fp16 operand (4 instructions
+// per pair, for loops bound by vector issue); otherwise hi is converted
+// back and subtracted (6 per pair, plain code the scheduler can interleave
+// with MFMAs, where the inline-asm form serialises).
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
@@ -68,26 +72,34 @@ __device__ __forceinline__ f32x16 mfma_f16(f16x8 a, f16x8 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
+template <bool FEW>
 __device__ __forceinline__ void split_f16x2(float x0, float x1, uint32_t part[2]) {
     const f32x2 x = {x0, x1};
-    const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, f16x2));
-    float r0, r1;
-    // r = x - hi with hi read as fp16 from its half of the packed word
-    asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r0) : "v"(h), "v"(x0));
-    asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
-        : "=v"(r1)
-        : "v"(h), "v"(x1));
-    const f32x2 r = {r0, r1};
+    const f16x2 hv = __builtin_convertvector(x, f16x2);
+    const uint32_t h = __builtin_bit_cast(uint32_t, hv);
+    f32x2 r;
+    if constexpr (FEW) {
+        float r0, r1;
+        // r = x - hi with hi read as fp16 from its half of the packed word
+        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r0) : "v"(h), "v"(x0));
+        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+            : "=v"(r1)
+            : "v"(h), "v"(x1));
+        r = f32x2{r0, r1};
+    } else {
+        r = x - __builtin_convertvector(hv, f32x2);
+    }
     part[0] = h;
     part[1] = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, f16x2));
 }
 
+template <bool FEW = true>
 __device__ __forceinline__ void split8_f16(const float (&v)[8], f16x8 (&o)[2]) {
     uint32_t w[2][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         uint32_t part[2];
-        split_f16x2(v[2 * j], v[2 * j + 1], part);
+        split_f16x2<FEW>(v[2 * j], v[2 * j + 1], part);
         w[0][j] = part[0];
         w[1][j] = part[1];
     }

@@ -104,7 +104,7 @@ template <int PREC>
 __device__ __forceinline__ void split8_planes(const float (&v)[8],
                                               typename WideCfg<PREC>::Frag (&o)[WideCfg<PREC>::NPL]) {
     if constexpr (PREC == 4)
-        split8_f16(v, o);
+        split8_f16<false>(v, o);  // interleaved with the MFMAs
     else
         split8_bf16<WideCfg<PREC>::NPL>(v, o);
 }
