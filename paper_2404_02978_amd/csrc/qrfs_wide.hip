@@ -115,21 +115,23 @@ __device__ __forceinline__ f32x16 mfma16(f16x8 a, f16x8 b, f32x16 c) { return mf
 // in [2^13, 2^14) (fp16 holds up to 65504): |w_k c_rk| <= max_k |w_k| times
 // the largest coefficient the generators can draw, 8.2 (Box-Muller radius
 // sqrt(-2 ln 2^-24) = 5.77 for the Gaussian pair, times sqrt(2) in the Eq. 3
-// form).  One block per set.
+// form).  One block of 1024 threads per set: each set is read once and the
+// reduction is latency-bound, so the block is made wide.
 constexpr double kCoefMax = 8.2;
 
-__global__ __launch_bounds__(256) void k_set_scale(const double* __restrict__ w, int64_t K,
-                                                   double* __restrict__ ascale) {
-    __shared__ double red[4];
+__global__ __launch_bounds__(1024) void k_set_scale(const double* __restrict__ w, int64_t K,
+                                                    double* __restrict__ ascale) {
+    __shared__ double red[16];
     const double* ws = w + (int64_t)blockIdx.x * K;
     double m = 0.0;
-    for (int64_t k = threadIdx.x; k < K; k += 256) m = fmax(m, fabs(ws[k]));
+    for (int64_t k = threadIdx.x; k < K; k += 1024) m = fmax(m, fabs(ws[k]));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
-        m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+#pragma unroll
+        for (int i = 1; i < 16; ++i) m = fmax(m, red[i]);
         double sc;
         float us;
         f16_scale(m * kCoefMax, sc, us);
@@ -618,7 +620,7 @@ hipError_t launch_wide_coef(int precision, const WideArgs& wa, hipStream_t st) {
 
 hipError_t launch_wide_scale(const double* w, int64_t K, int64_t n_sets, double* ascale,
                              hipStream_t st) {
-    hipLaunchKernelGGL(k_set_scale, dim3((unsigned)n_sets), dim3(256), 0, st, w, K, ascale);
+    hipLaunchKernelGGL(k_set_scale, dim3((unsigned)n_sets), dim3(1024), 0, st, w, K, ascale);
     return hipGetLastError();
 }
 
