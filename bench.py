@@ -221,7 +221,21 @@ def cpu_baseline(cfg, K, target_s):
     return {"value": R_s * K * nB / dt, "unit": "terms/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle, L0=25 m curve, {R_s} realisations x K={K} x {nB} baselines "
                       f"({dt:.1f} s); realisations/s = {R_s / dt:.1f}",
-            "realisations_per_s": R_s / dt}
+            "realisations_per_s": R_s / dt, "host": host_cpu()}
+
+
+def host_cpu():
+    """CPU model and the logical CPUs this process may run on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
 
 
 def traffic_bytes(args, K, R, Rb):
