@@ -18,7 +18,11 @@
  *     optical path instead (m, m^2 for structure functions, Sec. 4.4).
  *   - Array arguments are DEVICE pointers (memory of the context's device),
  *     contiguous, naturally aligned, owned by the caller, unless the comment
- *     says "host".  Struct arguments are host pointers.
+ *     says "host".  Struct arguments are host pointers.  Outputs must be
+ *     ordinary (coarse-grained) device memory, as hipMalloc returns: the
+ *     kernels for wide point sets add partial sums into them with device
+ *     float atomics, which host-mapped or fine-grained memory does not
+ *     support.
  *   - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL =
  *     the null stream) and the call returns after enqueueing; results are
  *     ready when the stream is synchronised.  Calls on one context must not
