@@ -6,7 +6,8 @@
 // Here the work is split in two phases:
 //   1. k_coef_tiles draws every coefficient of the launch once (Philox +
 //      Box-Muller, or the caller's array), splits it into the MFMA operand
-//      format (FP32, or 2 / 3 BF16 planes) and writes it to HBM already in
+//      format (FP32, 2 / 3 BF16 planes, or 2 fp16 planes scaled per set by
+//      k_set_scale) and writes it to HBM already in
 //      the per-lane order of the MFMA A operand: one 1 KiB fragment per
 //      (32 rows, 8 or 16 contraction values, plane), lane (r, h) holding
 //      row r and contraction values j = j0 + 4h + q (FP32, 4 values) or
@@ -26,10 +27,11 @@
 // Blocks are remapped so that the blocks one XCD runs together share a row
 // panel and walk the column tiles: each XCD streams a coefficient panel
 // through its own L2 once per round of blocks.
-// FP32-class precisions (FP32, BF16x6) contract K in ranges of about 2048
-// frequencies; at the end of each range a block adds its accumulators into
-// its output tile and clears them, so FP32 accumulation error grows with the
-// square root of the range, not of K.
+// FP32-class precisions (FP32, BF16x6, FP16x3) contract K in ranges of about
+// 2048 frequencies; at the end of each range a block stores (first range) or
+// adds (posted float atomics, later ranges) its accumulators into its output
+// tile and clears them, so FP32 accumulation error grows with the square
+// root of the range, not of K.
 #include "qrfs_mfma.hpp"
 
 namespace qrfs {
