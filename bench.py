@@ -61,9 +61,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=list(PREC_IDS), default="fp16x3")
-    ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "copy", "peaks"], default="bench",
                     help="copy: only a 1 GiB device-to-device copy, the reference for the "
-                         "HBM byte counters")
+                         "HBM byte counters; peaks: the measured ceilings of MFMA, vector "
+                         "FMA and HBM copy against the nominal peaks")
     ap.add_argument("--R", type=int, default=100000)
     ap.add_argument("--K", type=int, default=16384)
     ap.add_argument("--R-block", type=int, default=256)
@@ -308,8 +309,10 @@ def workload_large_screen(args):
     FP64 oracle on realisations 0..63 at 1024
     sampled points (max and RMS phase error in rad), also reported for the
     sampled points inside the circular pupil |x| <= 4 m; the pupil's own
-    point set (51 468 points) is timed too.  With --steps >= 2 the fused
-    kernel is timed for comparison at r0 = 0.1 m."""
+    point set (51 040 points) is timed too.  With --steps >= 2 the fused
+    kernel is timed for comparison at r0 = 0.1 m.  The MFMA ceilings the
+    device sustains on varied operands (libqrfs_peaks) are measured after
+    the runs, and each run's executed MFMA rate is also given against them."""
     import numpy as np
     import torch
     import paper_2404_02978_amd as q
@@ -344,16 +347,16 @@ def workload_large_screen(args):
                                 seed=base["seed"])
         oracle_s = time.perf_counter() - t
         runs = {"oracle_subset_s": oracle_s, "phase_rms_rad": float(np.sqrt(np.mean(ref ** 2)))}
-        cases = [("split_bf16", q.PREC_SPLIT_BF16, 3, 2500.0, 2),
-                 ("fp16x3", q.PREC_FP16X3, 3, 2500.0, 2),
-                 ("bf16x6", q.PREC_BF16X6, 6, 2500.0, 2),
-                 ("fp32", q.PREC_FP32, 1, 157.3, 2)]
+        cases = [("split_bf16", q.PREC_SPLIT_BF16, 3, 2500.0, 2, "mfma_bf16"),
+                 ("fp16x3", q.PREC_FP16X3, 3, 2500.0, 2, "mfma_fp16"),
+                 ("bf16x6", q.PREC_BF16X6, 6, 2500.0, 2, "mfma_bf16"),
+                 ("fp32", q.PREC_FP32, 1, 157.3, 2, "mfma_f32")]
         if r0 == 0.1 and args.steps >= 2:
-            cases += [("split_bf16_fused", q.PREC_SPLIT_BF16, 3, 2500.0, 1),
-                      ("fp16x3_fused", q.PREC_FP16X3, 3, 2500.0, 1),
-                      ("bf16x6_fused", q.PREC_BF16X6, 6, 2500.0, 1),
-                      ("fp32_fused", q.PREC_FP32, 1, 157.3, 1)]
-        for name, prec, passes, peak, path in cases:
+            cases += [("split_bf16_fused", q.PREC_SPLIT_BF16, 3, 2500.0, 1, "mfma_bf16"),
+                      ("fp16x3_fused", q.PREC_FP16X3, 3, 2500.0, 1, "mfma_fp16"),
+                      ("bf16x6_fused", q.PREC_BF16X6, 6, 2500.0, 1, "mfma_bf16"),
+                      ("fp32_fused", q.PREC_FP32, 1, 157.3, 1, "mfma_f32")]
+        for name, prec, passes, peak, path, probe in cases:
             ctx.set_tuning(q.TUNE_WIDE_PATH, path)
             if args.range_freqs:
                 ctx.set_tuning(q.TUNE_RANGE_FREQS, args.range_freqs)
@@ -368,6 +371,7 @@ def workload_large_screen(args):
             runs[name] = {"ms": ms, "terms_per_s": R * K * P / (ms * 1e-3),
                           "algorithmic_tflops": alg, "mfma_frac": alg / peak,
                           "executed_mfma_frac": alg * passes / peak,
+                          "executed_tflops": alg * passes, "ceiling_probe": probe,
                           "max_abs_err_rad": float(np.max(np.abs(d))),
                           "rms_abs_err_rad": float(np.sqrt(np.mean(d * d))),
                           "pupil_max_abs_err_rad": float(np.max(np.abs(d[:, inside]))),
@@ -391,6 +395,14 @@ def workload_large_screen(args):
         out["runs"][f"r0={r0}"] = runs
         print(json.dumps({f"r0={r0}": runs}), file=sys.stderr, flush=True)
     ctx.set_tuning(q.TUNE_WIDE_PATH, 0)
+    del phase, mphase
+    ceil = {k: probe_ceiling(k, repeats=3) for k in ("mfma_bf16", "mfma_fp16", "mfma_f32")}
+    out["measured_ceilings_tflops"] = {k: v["achieved"] for k, v in ceil.items()}
+    for runs in out["runs"].values():
+        for rec in runs.values():
+            if isinstance(rec, dict) and "ceiling_probe" in rec:
+                rec["executed_frac_of_measured"] = (rec["executed_tflops"] /
+                                                    ceil[rec["ceiling_probe"]]["achieved"])
     print(json.dumps(out), flush=True)
 
 
@@ -575,10 +587,100 @@ def copy_calibration():
     print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n}), flush=True)
 
 
+_X_MFMA, _X_FMA, _Y_FMA = 2.0 ** -6, 1.0, 2.0 ** -10
+
+
+def _probe_table():
+    """(kind, name, operand x (0: varied data), nominal flop/s or B/s, closed
+    form of the per-lane sums after `it` rounds, or None: linear in `it`)."""
+    from paper_2404_02978_amd import peaks as pk
+    x = _X_MFMA
+    return [
+        (pk.PEAK_MFMA_BF16, "mfma_bf16", 0.0, 2500e12, None),
+        (pk.PEAK_MFMA_FP16, "mfma_fp16", 0.0, 2500e12, None),
+        (pk.PEAK_MFMA_F32, "mfma_f32", 0.0, 157.3e12, None),
+        (pk.PEAK_MFMA_BF16, "mfma_bf16_const", x, 2500e12, lambda it: 64 * it * 16 * x * x),
+        (pk.PEAK_MFMA_FP16, "mfma_fp16_const", x, 2500e12, lambda it: 64 * it * 16 * x * x),
+        (pk.PEAK_MFMA_F32, "mfma_f32_const", x, 157.3e12, lambda it: 64 * it * 2 * x * x),
+        (pk.PEAK_VALU_F32, "valu_fma_f32", _X_FMA, 78.6e12, lambda it: 8 * it * _Y_FMA),
+        (pk.PEAK_VALU_F64, "valu_fma_f64", _X_FMA, 78.6e12, lambda it: 8 * it * _Y_FMA),
+        (pk.PEAK_HBM_COPY, "hbm_copy", 0.0, 8e12, None),
+    ]
+
+
+def probe_ceiling(name, repeats=5):
+    """Runs one probe of libqrfs_peaks: first checked against its expected
+    sums on a short run, then timed on one round of resident blocks (about
+    50 ms of nominal work), best of `repeats` launches timed with events on
+    the stream they run on.  Returns the probe's record (achieved and nominal
+    in TFLOP/s or TB/s)."""
+    import torch
+    from paper_2404_02978_amd import peaks as pk
+    kind, _, x, nominal, closed = next(p for p in _probe_table() if p[1] == name)
+    st = torch.cuda.current_stream()
+    blocks = pk.peak_blocks(kind)
+    y = _Y_FMA
+    if kind == pk.PEAK_HBM_COPY:
+        n = 1 << 28
+        src = torch.arange(n, dtype=torch.float32, device="cuda")
+        dst = torch.zeros_like(src)
+        out, iters, args_ = None, 0, (src, dst, n)
+        pk.peak_launch(kind, blocks, 0, x, y, None, src, dst, n, st)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst), "copy probe moved the wrong data"
+    else:
+        out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+        if closed is None:  # varied operands: the sums are linear in the rounds
+            pk.peak_launch(kind, blocks, 1, x, y, out, None, None, 0, st)
+            ref = 16 * out.clone()
+        w16 = pk.peak_launch(kind, blocks, 16, x, y, out, None, None, 0, st)
+        torch.cuda.synchronize()
+        expect = ref if closed is None else closed(16)
+        bad = int((out != expect).sum())
+        assert bad == 0, f"{name}: {bad} lanes differ from the expected sums"
+        if closed is None:
+            assert bool((ref != 0).any()), f"{name}: all sums are zero"
+        iters = max(16, int(0.05 * nominal / (w16 / 16)))
+        args_ = (None, None, 0)
+    work = pk.peak_launch(kind, blocks, iters, x, y, out, *args_, st)  # warm-up
+    best = 0.0
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        pk.peak_launch(kind, blocks, iters, x, y, out, *args_, st)
+        e1.record(st)
+        torch.cuda.synchronize()
+        best = max(best, work / (e0.elapsed_time(e1) * 1e-3))
+    return {"achieved": best / 1e12, "nominal": nominal / 1e12,
+            "unit": "TB/s" if kind == pk.PEAK_HBM_COPY else "TFLOP/s",
+            "operands": ("varied" if x == 0.0 else "constant")
+            if kind <= pk.PEAK_MFMA_F32 else None,
+            "frac": best / nominal, "blocks": blocks, "iters": iters}
+
+
+def measure_peaks():
+    """Throughput the device sustains per instruction class (libqrfs_peaks):
+    dense MFMA in bf16, fp16 and FP32 on varied and on constant operands,
+    unpacked vector FMA in FP32 and FP64, and a streaming copy, each against
+    MI355X's nominal peak."""
+    import torch
+    out_json = {"mode": "peaks", "device": torch.cuda.get_device_name(0), "probes": {}}
+    for p in _probe_table():
+        out_json["probes"][p[1]] = probe_ceiling(p[1])
+    # matrix-core clock implied by the bf16 probes (2.4 GHz nominal)
+    out_json["implied_mfma_clock_ghz"] = {
+        k: 2.4 * out_json["probes"][k]["frac"] for k in ("mfma_bf16", "mfma_bf16_const")}
+    print(json.dumps(out_json), flush=True)
+
+
 def main():
     args = parse()
     if args.mode == "copy":
         copy_calibration()
+        return
+    if args.mode == "peaks":
+        measure_peaks()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -699,6 +801,23 @@ def main():
                 "executed_mfma": {"passes": passes, "tflops": achieved * passes,
                                   "frac": achieved * passes / PEAKS[args.precision]},
                 "alu_view": alu_view}
+
+    # the same instruction classes measured on this device (libqrfs_peaks),
+    # outside the timed region: a busy MI355X holds a clock below 2.4 GHz,
+    # and lower still when the matrix cores see changing data
+    meas = {}
+    mfma_probe = {"fp16x3": "mfma_fp16", "split_bf16": "mfma_bf16", "bf16x6": "mfma_bf16",
+                  "fp32": "mfma_f32"}.get(args.precision)
+    if mfma_probe and "executed_mfma" in roof:
+        m = probe_ceiling(mfma_probe, repeats=3)
+        meas["mfma"] = {"probe": mfma_probe + " (varied operands)", "achieved": m["achieved"],
+                        "unit": "TFLOP/s",
+                        "executed_frac": roof["executed_mfma"]["tflops"] / m["achieved"]}
+    v = probe_ceiling("valu_fma_f32", repeats=3)
+    meas["valu"] = {"probe": "valu_fma_f32", "achieved": v["achieved"] / 2,
+                    "unit": "T lane-ops/s",
+                    "alu_view_frac": alu_view["achieved"] / (v["achieved"] / 2)}
+    roof["measured_ceilings"] = meas
 
     # the same workload with the FP32 MFMA contraction, for reference
     fp32_ref = None

@@ -178,3 +178,30 @@ def test_choose_cartesian_optical_path_and_not_converged(q):
     with pytest.raises(q.QrfsError) as e:
         q.choose_cartesian(q.psd(0.1, 22.0, wavelength=-1.0), None, 0.0, 1e-3)
     assert e.value.status == q.ERR_INVALID_ARG
+
+
+def test_peaks_library_exports_and_checks():
+    """libqrfs_peaks (the roofline probes of bench.py --mode peaks) exports
+    what include/qrfs_peaks.h declares and refuses bad arguments before any
+    device call."""
+    from paper_2404_02978_amd import peaks as pk
+    if not os.path.exists(pk.PEAKS_LIB_PATH):
+        from paper_2404_02978_amd import build
+        build.build()
+    lib = pk.load_peaks()
+    text = open(os.path.join(ROOT, "include", "qrfs_peaks.h")).read()
+    names = sorted(set(re.findall(r"QRFS_PEAKS_API\s+[\w\s\*]+?\b(qrfs_\w+)\s*\(", text)))
+    assert names == ["qrfs_peak_blocks", "qrfs_peak_launch"]
+    for n in names:
+        assert hasattr(lib, n), n
+    w = ctypes.c_double(0.0)
+    p = _null()
+    assert lib.qrfs_peak_launch(pk.PEAK_MFMA_BF16, 1, 1, 1.0, 0.0, p, None, None, 0, None,
+                                None) == -1  # no work pointer
+    assert lib.qrfs_peak_launch(pk.PEAK_MFMA_BF16, 0, 1, 1.0, 0.0, p, None, None, 0,
+                                ctypes.byref(w), None) == -1  # no blocks
+    assert lib.qrfs_peak_launch(pk.PEAK_HBM_COPY, 1, 0, 0.0, 0.0, None, p, p, 6,
+                                ctypes.byref(w), None) == -1  # n not a multiple of 4
+    assert lib.qrfs_peak_launch(99, 1, 1, 1.0, 0.0, p, None, None, 0, ctypes.byref(w),
+                                None) == -1  # unknown kind
+    assert lib.qrfs_peak_blocks(pk.PEAK_MFMA_BF16, None) == -1
