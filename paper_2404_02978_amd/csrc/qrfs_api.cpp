@@ -292,9 +292,13 @@ qrfs_status wide_sum(qrfs_context* ctx, int precision, int basis, qrfs::SumArgs 
     const int64_t cts = cdiv(a.P, 256);
     const int64_t rts_set = cdiv(a.R_block, 256);
     // coefficient tiles take at most ctx->tile_cap of workspace per piece
-    // (one 256-row block of one set at least)
+    // (one 256-row block of one set at least); behind them the store sink
+    // (256 B) and, for FP16X3, one scale per set
+    const size_t scale_bytes =
+        precision == QRFS_PREC_FP16X3 ? align256((size_t)n_sets * sizeof(double)) : 0;
     size_t cap = ctx->tile_cap;
-    if (ctx->ws_cap && ctx->ws_cap < cap + 512) cap = ctx->ws_cap > 512 ? ctx->ws_cap - 512 : 0;
+    const size_t extra = 512 + scale_bytes;
+    if (ctx->ws_cap && ctx->ws_cap < cap + extra) cap = ctx->ws_cap > extra ? ctx->ws_cap - extra : 0;
     const size_t set_bytes = (size_t)rts_set * 8 * row32;
     int64_t sets_piece = 1, rows_piece = a.R_block;
     if (set_bytes <= cap) {
@@ -308,8 +312,6 @@ qrfs_status wide_sum(qrfs_context* ctx, int precision, int basis, qrfs::SumArgs 
         rows_piece = (tiles < 1 ? 1 : tiles) * 256;
     }
     const size_t tile_bytes = align256((size_t)sets_piece * cdiv(rows_piece, 256) * 8 * row32);
-    const size_t scale_bytes =
-        precision == QRFS_PREC_FP16X3 ? align256((size_t)n_sets * sizeof(double)) : 0;
     qrfs_status s = ensure_workspace(ctx, tile_bytes + 256 + scale_bytes);
     if (s) return s;
     double* ascale = (double*)((char*)ctx->ws + tile_bytes + 256);
