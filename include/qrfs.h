@@ -267,13 +267,20 @@ typedef struct {
 
 /* ---------------------------------------------------------- entry points */
 
+/* Largest number of frequencies one sampling or weight call handles (one
+ * launch: 2^32 - 2^20, about 4.3e9, i.e. 103 GB of fx, fy and weights). */
+#define QRFS_MAX_POINTS_PER_CALL ((int64_t)4293918720)
+
 /* R2 frequency sampling (Sec. 3.2, Eqs. 5-6).  Writes n_sets*K points
  * (set-major: set s occupies [s*K, (s+1)*K)) to fx, fy (cycles/m) and the
  * cell area each point stands for to area (m^-2), all double[n_sets*K].
  * Cell areas are per set of K points.  s->index += n_sets*K on success.
- * Errors: K, n_sets <= 0; NULL pointers; Cartesian N <= 0 or df <= 0;
- * log-polar fmin <= 0 or fmax <= fmin; LEARNED without a proposal or
- * before its table was built. */
+ * One call draws at most QRFS_MAX_POINTS_PER_CALL points (one launch);
+ * larger sets of points are drawn in several calls, which continue the
+ * sequence from s->index.
+ * Errors: K, n_sets <= 0; n_sets*K > QRFS_MAX_POINTS_PER_CALL; NULL
+ * pointers; Cartesian N <= 0 or df <= 0; log-polar fmin <= 0 or
+ * fmax <= fmin; LEARNED without a proposal or before its table was built. */
 QRFS_API qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s, int64_t n_sets,
                                     int64_t K, double* fx, double* fy, double* area,
                                     void* stream);
@@ -292,8 +299,9 @@ QRFS_API qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s,
  *   binary32 Hankel branch (absolute error ~3e-8 of the unfiltered
  *   weight); cheaper to evaluate (mostly binary32 work instead of binary64).
  *   The frequencies are the same in both modes.
- * Errors: n <= 0; NULL arrays; r0 <= 0; von Karman L0 <= 0; unknown model;
- * ap with D <= 0, d < 0 or d >= D; unknown precision. */
+ * Errors: n <= 0 or n > QRFS_MAX_POINTS_PER_CALL; NULL arrays; r0 <= 0;
+ * von Karman L0 <= 0; unknown model; ap with D <= 0, d < 0 or d >= D;
+ * unknown precision. */
 QRFS_API qrfs_status qrfs_weights(qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aperture* ap,
                          int64_t n, const double* fx, const double* fy, const double* area,
                          int32_t precision, double* w, void* stream);

@@ -517,8 +517,10 @@ qrfs_status qrfs_sample_frequencies(qrfs_context* ctx, qrfs_sampler* s, int64_t 
     if (K <= 0 || n_sets <= 0)
         return fail(QRFS_ERR_INVALID_ARG, "K and n_sets must be > 0 (got %lld, %lld)",
                     (long long)K, (long long)n_sets);
-    if (n_sets > INT64_MAX / K || n_sets * K > ((int64_t)1 << 40))
-        return fail(QRFS_ERR_INVALID_ARG, "n_sets * K too large");
+    if (n_sets > INT64_MAX / K || n_sets * K > QRFS_MAX_POINTS_PER_CALL)
+        return fail(QRFS_ERR_INVALID_ARG, "n_sets * K = %lld exceeds %lld points per call",
+                    (long long)(n_sets > INT64_MAX / K ? INT64_MAX : n_sets * K),
+                    (long long)QRFS_MAX_POINTS_PER_CALL);
     CHECK_PTR(fx);
     CHECK_PTR(fy);
     CHECK_PTR(area);
@@ -546,7 +548,9 @@ qrfs_status qrfs_weights(qrfs_context* ctx, const qrfs_psd* psd, const qrfs_aper
     if (st) return st;
     if (ap && (st = check_ap(ap))) return st;
     if ((st = check_weight_precision(precision))) return st;
-    if (n <= 0) return fail(QRFS_ERR_INVALID_ARG, "n must be > 0 (got %lld)", (long long)n);
+    if (n <= 0 || n > QRFS_MAX_POINTS_PER_CALL)
+        return fail(QRFS_ERR_INVALID_ARG, "n must be in 1..%lld (got %lld)",
+                    (long long)QRFS_MAX_POINTS_PER_CALL, (long long)n);
     CHECK_PTR(fx);
     CHECK_PTR(fy);
     CHECK_PTR(area);
@@ -574,8 +578,10 @@ qrfs_status qrfs_sample_weights(qrfs_context* ctx, qrfs_sampler* s, int64_t n_se
     if (K <= 0 || n_sets <= 0)
         return fail(QRFS_ERR_INVALID_ARG, "K and n_sets must be > 0 (got %lld, %lld)",
                     (long long)K, (long long)n_sets);
-    if (n_sets > INT64_MAX / K || n_sets * K > ((int64_t)1 << 40))
-        return fail(QRFS_ERR_INVALID_ARG, "n_sets * K too large");
+    if (n_sets > INT64_MAX / K || n_sets * K > QRFS_MAX_POINTS_PER_CALL)
+        return fail(QRFS_ERR_INVALID_ARG, "n_sets * K = %lld exceeds %lld points per call",
+                    (long long)(n_sets > INT64_MAX / K ? INT64_MAX : n_sets * K),
+                    (long long)QRFS_MAX_POINTS_PER_CALL);
     CHECK_PTR(fx);
     CHECK_PTR(fy);
     CHECK_PTR(w);

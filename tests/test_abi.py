@@ -97,6 +97,17 @@ def test_argument_checks_precede_device_use(q):
     st = lib.qrfs_sample_frequencies(None, ctypes.byref(s), 1, 8, p, p, p, None)
     assert st == q.ERR_INVALID_ARG and b"proposal" in lib.qrfs_last_error_detail()
     assert s.index == 0  # untouched on error
+    # one call handles at most 2^32 - 2^20 points (one launch)
+    big = 4293918720
+    s = q.logpolar_sampler(1e-3, 1e2)
+    st = lib.qrfs_sample_frequencies(None, ctypes.byref(s), 2, big // 2 + 1, p, p, p, None)
+    assert st == q.ERR_INVALID_ARG and b"points per call" in lib.qrfs_last_error_detail()
+    st = lib.qrfs_sample_weights(None, ctypes.byref(s), 1, big + 1, ctypes.byref(q.psd(0.1, 25.0)),
+                                 None, 0, p, p, p, None)
+    assert st == q.ERR_INVALID_ARG and b"points per call" in lib.qrfs_last_error_detail()
+    st = lib.qrfs_weights(None, ctypes.byref(q.psd(0.1, 25.0)), None, big + 1, p, p, p, 0, p, None)
+    assert st == q.ERR_INVALID_ARG and b"must be in" in lib.qrfs_last_error_detail()
+    assert s.index == 0
     # coefficients without rng
     st = lib.qrfs_synthesize_phase(None, 10, p, p, p, 4, p, p, 5, 5, None, None, 1, p, None)
     assert st == q.ERR_INVALID_ARG

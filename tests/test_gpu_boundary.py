@@ -96,6 +96,26 @@ def test_workspace_cap(q):
     assert np.array_equal(res[0], res[1])
 
 
+def test_workspace_cap_fp16x3_many_sets(q):
+    """FP16x3 in the two-phase kernel keeps one tile scale per set behind the
+    coefficient tiles: under a cap that splits 64 sets into pieces the
+    result equals the uncapped one bit for bit."""
+    K, P, R, R_block = 1500, 1500, 64 * 128, 128
+    rng = np.random.default_rng(4)
+    px, py = dev(rng.uniform(-2, 2, P)), dev(rng.uniform(-2, 2, P))
+    res = []
+    for cap in (0, 8 << 20):
+        with q.Context(0, workspace_cap=cap) as ctx:
+            ctx.set_tuning(q.TUNE_WIDE_PATH, 2)
+            s = q.logpolar_sampler(1e-3, 1e2)
+            fx, fy, area = ctx.sample_frequencies(s, R // R_block, K)
+            w = ctx.weights(q.psd(0.1, 25.0), fx, fy, area)
+            res.append(host(ctx.synthesize_phase(K, fx, fy, w, px, py, R, R_block,
+                                                 rng=q.Rng(5, 0, 0), precision=q.PREC_FP16X3)))
+    assert np.all(np.isfinite(res[0]))
+    assert np.array_equal(res[0], res[1])
+
+
 def test_autotune_cache(q, tmp_path):
     """The first autotune of a batch times it and appends its choice to the
     cache; a batch of the same sizes then takes the stored choice."""
