@@ -494,7 +494,7 @@ QRFS_API qrfs_status qrfs_temporal_piston_structure(
  * in a fixed order (bit-reproducible).  O(K^2) work per set.
  * fx, fy: device double[n_sets*K]; min_dist, l2_star: device double[n_sets];
  * n_clash: device int64[n_sets].  Uses the context's workspace.
- * Errors: n_sets, K < 1; K > 2^24; n_sets * ceil(K/256) >= 2^31; Lx, Ly not
+ * Errors: n_sets, K < 1; K > 2^24; n_sets * ceil(K/256) >= 2^24; Lx, Ly not
  * > 0 or x0, y0 not finite; r_clash < 0; NULL or misaligned arrays. */
 QRFS_API qrfs_status qrfs_point_set_measures(qrfs_context* ctx, int64_t n_sets, int64_t K,
                                              const double* fx, const double* fy, double x0,
@@ -513,7 +513,7 @@ QRFS_API qrfs_status qrfs_point_set_measures(qrfs_context* ctx, int64_t n_sets, 
  * to [-1/2, 1/2] in FP64; FP64 sums in a fixed order.
  * fx, fy, w: device double[n_sets*K]; bx, by: device double[nB];
  * S: device double[n_sets][nB].
- * Errors: K, n_sets, nB < 1; n_sets >= 2^31; NULL or misaligned arrays. */
+ * Errors: K, n_sets, nB < 1; n_sets >= 2^24; NULL or misaligned arrays. */
 QRFS_API qrfs_status qrfs_set_sf_expectation(qrfs_context* ctx, int64_t K, const double* fx,
                                              const double* fy, const double* w, int64_t n_sets,
                                              int64_t nB, const double* bx, const double* by,
@@ -548,7 +548,7 @@ QRFS_API qrfs_status qrfs_proposal_destroy(qrfs_proposal* p);
 QRFS_API qrfs_status qrfs_proposal_get_params(const qrfs_proposal* p, float* dst, void* stream);
 QRFS_API qrfs_status qrfs_proposal_set_params(qrfs_proposal* p, const float* src, void* stream);
 /* Network outputs out[n][2] (o0, o1) for rows ell[n] with contexts
- * ctx4[n][4] = (D, L0, |B|, theta_B); all device. */
+ * ctx4[n][4] = (D, L0, |B|, theta_B); all device.  1 <= n <= 2^30 - 2^16. */
 QRFS_API qrfs_status qrfs_proposal_forward(qrfs_proposal* p, int64_t n, const double* ell,
                                            const double* ctx4, float* out, void* stream);
 /* Training rows from the plain log-polar sampler `plain` (advanced by
@@ -556,21 +556,23 @@ QRFS_API qrfs_status qrfs_proposal_forward(qrfs_proposal* p, int64_t n, const do
  * with ell, theta and the contribution
  * h = f^2 W(f) F_D(f)^2 2 (1 - cos(2 pi f |B| cos(theta - theta_B)))
  * of a von Karman PSD with Fried parameter r0 (c_psd <= 0: exact constant)
- * and outer scale L0 of the context.  Outputs device double[n_ctx*m]. */
+ * and outer scale L0 of the context.  Outputs device double[n_ctx*m];
+ * n_ctx * m <= QRFS_MAX_POINTS_PER_CALL. */
 QRFS_API qrfs_status qrfs_proposal_rows(qrfs_proposal* p, qrfs_sampler* plain, int64_t n_ctx,
                                         int64_t m, const double* ctx4, double r0, double c_psd,
                                         double* ell, double* theta, double* h, void* stream);
 /* Loss and its gradient for all n_ctx contexts of a training set (the
  * training step's computation, exposed for checking): grad device
  * float[QRFS_PROPOSAL_NPARAM], loss device double[1].  G: normaliser grid
- * points (1..4096).  n_ctx <= 1024. */
+ * points (1..4096).  n_ctx <= 1024, n_ctx * m <= 2^29. */
 QRFS_API qrfs_status qrfs_proposal_loss_grad(qrfs_proposal* p, int64_t n_ctx, int64_t m,
                                              const double* ctx4, const double* ell,
                                              const double* theta, const double* h, int32_t G,
                                              float* grad, double* loss, void* stream);
 /* `steps` Adam steps (learning rate lr) on mini-batches of ctx_per_step
- * contexts (<= 1024) taken in an order reshuffled every epoch from
- * shuffle_seed; loss_log: device double[steps] or NULL. */
+ * contexts (<= 1024, ctx_per_step * m <= 2^29) taken in an order
+ * reshuffled every epoch from shuffle_seed; loss_log: device double[steps]
+ * or NULL. */
 QRFS_API qrfs_status qrfs_proposal_train(qrfs_proposal* p, int64_t n_ctx, int64_t m,
                                          const double* ctx4, const double* ell,
                                          const double* theta, const double* h,

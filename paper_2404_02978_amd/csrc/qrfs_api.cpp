@@ -734,8 +734,10 @@ qrfs_status qrfs_point_set_measures(qrfs_context* ctx, int64_t n_sets, int64_t K
                     (long long)n_sets, (long long)K);
     if (K > ((int64_t)1 << 24))
         return fail(QRFS_ERR_INVALID_ARG, "K must be <= 2^24 (got %lld)", (long long)K);
-    if (n_sets * qrfs::measure_tiles(K) >= ((int64_t)1 << 31))
-        return fail(QRFS_ERR_INVALID_ARG, "n_sets * ceil(K/256) must be < 2^31");
+    // one block of 256 threads per (set, 256-point tile): at most 2^24
+    // blocks keep the launch within 2^32 work-items
+    if (n_sets * qrfs::measure_tiles(K) >= ((int64_t)1 << 24))
+        return fail(QRFS_ERR_INVALID_ARG, "n_sets * ceil(K/256) must be < 2^24");
     if (!(Lx > 0.0) || !(Ly > 0.0) || !std::isfinite(Lx) || !std::isfinite(Ly) ||
         !std::isfinite(x0) || !std::isfinite(y0))
         return fail(QRFS_ERR_INVALID_ARG, "the unit-square map needs finite x0, y0 and Lx, Ly > 0");
@@ -764,8 +766,8 @@ qrfs_status qrfs_set_sf_expectation(qrfs_context* ctx, int64_t K, const double* 
                                     const double* bx, const double* by, double* S, void* stream) {
     if (K < 1 || n_sets < 1 || nB < 1)
         return fail(QRFS_ERR_INVALID_ARG, "K, n_sets and nB must be >= 1");
-    if (n_sets >= ((int64_t)1 << 31))
-        return fail(QRFS_ERR_INVALID_ARG, "n_sets must be < 2^31");
+    if (n_sets >= ((int64_t)1 << 24))  // one 256-thread block per set
+        return fail(QRFS_ERR_INVALID_ARG, "n_sets must be < 2^24");
     CHECK_PTR(fx);
     CHECK_PTR(fy);
     CHECK_PTR(w);

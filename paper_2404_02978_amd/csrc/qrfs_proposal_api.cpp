@@ -12,6 +12,11 @@
 #include "qrfs_internal.hpp"
 #include "qrfs_proposal.hpp"
 
+// rows of one loss/gradient or training step (plus at most 4M grid rows):
+// the network kernels take 64 rows per 256-thread block, so this keeps a
+// launch well within 2^32 work-items
+static constexpr int64_t kMaxStepRows = (int64_t)1 << 29;
+
 namespace qrfs {
 qrfs_status api_fail(qrfs_status s, const char* fmt, ...);
 qrfs_status api_ok();
@@ -210,7 +215,10 @@ qrfs_status qrfs_proposal_set_params(qrfs_proposal* p, const float* src, void* s
 qrfs_status qrfs_proposal_forward(qrfs_proposal* p, int64_t n, const double* ell,
                                   const double* ctx4, float* out, void* stream) {
     if (!p) return api_fail(QRFS_ERR_INVALID_ARG, "proposal is NULL");
-    if (n <= 0 || n > ((int64_t)1 << 36)) return api_fail(QRFS_ERR_INVALID_ARG, "bad n");
+    // 64 points per 256-thread block: at most 2^30 - 2^16 points keep the
+    // launch within 2^32 work-items
+    if (n <= 0 || n > ((int64_t)1 << 30) - ((int64_t)1 << 16))
+        return api_fail(QRFS_ERR_INVALID_ARG, "n must be in 1..2^30 - 2^16");
     if (!ell || !ctx4 || !out || !al8(ell) || !al8(ctx4) || !al4(out))
         return api_fail(QRFS_ERR_INVALID_ARG, "NULL or misaligned array");
     Guard g(p->device);
@@ -227,8 +235,9 @@ qrfs_status qrfs_proposal_rows(qrfs_proposal* p, qrfs_sampler* plain, int64_t n_
         return api_fail(QRFS_ERR_INVALID_ARG, "training rows need the plain log-polar sampler");
     if (plain->fmin != p->fmin || plain->fmax != p->fmax)
         return api_fail(QRFS_ERR_INVALID_ARG, "sampler band differs from the proposal's");
-    if (n_ctx <= 0 || m <= 0 || n_ctx * m > ((int64_t)1 << 34))
-        return api_fail(QRFS_ERR_INVALID_ARG, "bad n_ctx or m");
+    if (n_ctx <= 0 || m <= 0 || n_ctx > QRFS_MAX_POINTS_PER_CALL / m)
+        return api_fail(QRFS_ERR_INVALID_ARG,
+                        "n_ctx and m must be >= 1 with n_ctx * m <= QRFS_MAX_POINTS_PER_CALL");
     if (!(r0 > 0.0)) return api_fail(QRFS_ERR_INVALID_ARG, "r0 must be > 0");
     if (!ctx4 || !ell || !theta || !h || !al8(ctx4) || !al8(ell) || !al8(theta) || !al8(h))
         return api_fail(QRFS_ERR_INVALID_ARG, "NULL or misaligned array");
@@ -249,6 +258,9 @@ qrfs_status qrfs_proposal_loss_grad(qrfs_proposal* p, int64_t n_ctx, int64_t m,
     if (!p) return api_fail(QRFS_ERR_INVALID_ARG, "proposal is NULL");
     if (n_ctx <= 0 || n_ctx > 1024 || m <= 0 || G < 1 || G > 4096)
         return api_fail(QRFS_ERR_INVALID_ARG, "need 1 <= n_ctx <= 1024, m >= 1, 1 <= G <= 4096");
+    // rows of one step, 64 per 256-thread block, within 2^32 work-items
+    if (n_ctx * m > kMaxStepRows)
+        return api_fail(QRFS_ERR_INVALID_ARG, "n_ctx * m must be <= 2^29");
     if (!ctx4 || !ell || !theta || !h || !grad || !al8(ctx4) || !al8(ell) || !al8(theta) ||
         !al8(h) || !al4(grad) || (loss && !al8(loss)))
         return api_fail(QRFS_ERR_INVALID_ARG, "NULL or misaligned array");
@@ -278,6 +290,8 @@ qrfs_status qrfs_proposal_train(qrfs_proposal* p, int64_t n_ctx, int64_t m, cons
         ctx_per_step > n_ctx || steps <= 0 || G < 1 || G > 4096 || !(lr > 0.0))
         return api_fail(QRFS_ERR_INVALID_ARG, "bad training sizes or learning rate");
     if (n_ctx > 0x7fffffff) return api_fail(QRFS_ERR_INVALID_ARG, "too many contexts");
+    if (ctx_per_step * m > kMaxStepRows)
+        return api_fail(QRFS_ERR_INVALID_ARG, "ctx_per_step * m must be <= 2^29");
     if (!ctx4 || !ell || !theta || !h || !al8(ctx4) || !al8(ell) || !al8(theta) || !al8(h) ||
         (loss_log && !al8(loss_log)))
         return api_fail(QRFS_ERR_INVALID_ARG, "NULL or misaligned array");
