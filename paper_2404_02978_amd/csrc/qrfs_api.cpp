@@ -237,14 +237,18 @@ hipError_t sample_weights_any(const qrfs_sampler* s, uint64_t index, int64_t n_s
                                        has_ap, D, d, f32, fx, fy, w, st);
 }
 
+// Largest grid of one launch: the work-items of a dispatch (blocks x
+// threads, at most 1024 threads per block here) must fit in 32 bits.
+constexpr int64_t kMaxLaunchBlocks = (int64_t)1 << 22;
+
 // Runs launch_sum over all sets, splitting the grid so no launch exceeds
-// 2^30 blocks.
+// kMaxLaunchBlocks blocks.
 qrfs_status run_sum(int precision, int basis, int epi, qrfs::SumArgs a, int64_t n_sets,
                     hipStream_t st) {
     int64_t rts = qrfs::sum_row_tiles_per_set(precision, basis, a.R_block, a.P);
     int64_t cts = qrfs::sum_col_tiles(precision, basis, a.R_block, a.P);
     int64_t per_set = rts * cts * (a.ksplit > 1 ? a.ksplit : 1);
-    int64_t max_sets = ((int64_t)1 << 30) / (per_set > 0 ? per_set : 1);
+    int64_t max_sets = kMaxLaunchBlocks / (per_set > 0 ? per_set : 1);
     if (max_sets < 1) return fail(QRFS_ERR_INVALID_ARG, "problem too large for one set");
     const double* fx0 = a.fx;
     const double* fy0 = a.fy;
@@ -303,7 +307,7 @@ qrfs_status wide_sum(qrfs_context* ctx, int precision, int basis, qrfs::SumArgs 
     int64_t sets_piece = 1, rows_piece = a.R_block;
     if (set_bytes <= cap) {
         sets_piece = (int64_t)(cap / set_bytes);
-        const int64_t max_blocks = (int64_t)1 << 30;
+        const int64_t max_blocks = kMaxLaunchBlocks;
         if (sets_piece * rts_set * cts > max_blocks) sets_piece = max_blocks / (rts_set * cts);
         if (sets_piece < 1) return fail(QRFS_ERR_INVALID_ARG, "problem too large for one set");
         if (sets_piece > n_sets) sets_piece = n_sets;
