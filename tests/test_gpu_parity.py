@@ -60,12 +60,14 @@ def report(name, got, ref, tol):
 
 # ------------------------------------------------------------- sampler ----
 
-@pytest.mark.parametrize("index", [0, 12345, (1 << 40) + 7])
+@pytest.mark.parametrize("index", [0, 12345, (1 << 40) + 7, (1 << 64) - 1500])
 def test_sampler_cartesian_bit_exact(q, ctx, index):
+    """Points bit for bit; the last index runs the 64-bit state across its
+    wrap (the exact Weyl sequence is periodic mod 2^64), on both sides."""
     n_sets, K, N, df = 3, 1000, 44, 0.25 / 22
     s = q.cartesian_sampler(N, df, index=index)
     fx, fy, area = ctx.sample_frequencies(s, n_sets, K)
-    assert s.index == index + n_sets * K
+    assert s.index == (index + n_sets * K) % (1 << 64)
     rx, ry, ra = oracle.sample_cartesian(n_sets, K, N, df, index=index)
     assert np.array_equal(host(fx), rx) and np.array_equal(host(fy), ry)
     assert np.array_equal(host(area), ra)
