@@ -73,6 +73,27 @@ def test_sampler_cartesian_bit_exact(q, ctx, index):
     assert np.array_equal(host(area), ra)
 
 
+def test_synthesize_split_launches(q, ctx):
+    """5e6 realisations with fresh frequencies each (R_block = 1): more sets
+    than one launch takes (2^22 blocks), so the contraction runs in several
+    launches; realisations on both sides of each cut and the last one match
+    the oracle."""
+    K, R = 8, 5_000_000
+    gx, gy = np.meshgrid(np.linspace(-0.5, 0.5, 8), np.linspace(-0.5, 0.5, 8))
+    px, py = gx.ravel(), gy.ravel()
+    s = q.logpolar_sampler(1e-3, 1e2)
+    fx, fy, area = ctx.sample_frequencies(s, R, K)
+    w = ctx.weights(q.psd(0.1, 25.0), fx, fy, area)
+    out = ctx.synthesize_phase(K, fx, fy, w, dev(px), dev(py), R, 1, rng=q.Rng(7, 0, 0),
+                               precision=q.PREC_FP32)
+    for r in (0, (1 << 21) - 1, 1 << 21, (1 << 22) - 1, 1 << 22, (1 << 22) + 1, R - 1):
+        sl = slice(r * K, (r + 1) * K)
+        ref = oracle.synthesize(host(fx[sl]), host(fy[sl]), host(w[sl]), px, py, 1, 1, K=K,
+                                seed=7, counter=r)
+        report(f"split launches, realisation {r}", host(out[r:r + 1]), ref, 1e-5)
+    del out, fx, fy, area, w
+
+
 def test_sampler_logpolar(q, ctx):
     n_sets, K = 2, 777
     s = q.logpolar_sampler(1e-3, 1e2, index=99, seed_x=3 << 60, seed_y=5 << 59)
