@@ -58,8 +58,8 @@ extern "C" {
  * launch of that many blocks fills the device in a single round. */
 QRFS_PEAKS_API int qrfs_peak_blocks(int kind, int64_t* blocks);
 
-/* Launches one probe of `kind` with `blocks` blocks of 256 threads (out
- * holds blocks * 256 floats).  *work receives the launch's nominal work:
+/* Launches one probe of `kind` with `blocks` blocks of 256 threads
+ * (1 <= blocks < 2^24; out holds blocks * 256 floats).  *work receives the launch's nominal work:
  * flops for the MFMA and VALU kinds (2 per multiply-add), bytes moved
  * (read + written) for HBM_COPY. */
 QRFS_PEAKS_API int qrfs_peak_launch(int kind, int64_t blocks, int32_t iters, float x, float y,

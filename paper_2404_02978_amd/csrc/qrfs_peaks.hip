@@ -162,7 +162,8 @@ extern "C" int qrfs_peak_launch(int kind, int64_t blocks, int32_t iters, float x
                                 float* out, const float* src, float* dst, int64_t n,
                                 double* work, void* stream) {
     hipStream_t st = (hipStream_t)stream;
-    if (!work || blocks < 1 || blocks > (int64_t)1 << 24) return -1;
+    // blocks x 256 work-items must fit in 32 bits
+    if (!work || blocks < 1 || blocks >= (int64_t)1 << 24) return -1;
     const dim3 grid((unsigned)blocks), block(kThreads);
     const double lanes = (double)blocks * kThreads;
     const double waves = (double)blocks * (kThreads / 64);
